@@ -1,0 +1,78 @@
+/*
+ * orc.h -- FP64 CPU oracle of the split-step round-trip map of a
+ * microchip-laser cavity (Okulov, "Two-dimensional periodic and
+ * quasiperiodic spatial structures in microchip laser resonator").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain, obviously
+ * correct reference that the GPU path is checked against.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark load it.
+ * It shares no code, header, table or constant with the GPU library.
+ *
+ * Complex arrays are interleaved (re, im) doubles.  N x N grids are
+ * row-major: element (row y, column x) sits at index y*N + x.
+ */
+#ifndef ORC_H
+#define ORC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int    N;           /* grid points per side                               */
+    double dx;          /* grid spacing (m)                                   */
+    double lambda;      /* wavelength (m)                                     */
+    double L;           /* propagation length of one map iterate (m)          */
+    double focal;       /* mirror focal length (m), < 0 diverging; 0 or inf = flat */
+    double R;           /* mirror (intensity) reflectivity, 0 < R <= 1         */
+    int    ap_kind;     /* 0 none, 1 super-Gaussian, 2 Gaussian, 3 user mask   */
+    double ap_radius;   /* aperture radius r0 (m)                             */
+    int    ap_order;    /* super-Gaussian exponent m in exp(-(r/r0)^m)        */
+    const double* ap_mask; /* kind 3: N*N real amplitude, row-major           */
+    double N0;          /* pump level (round-trip log-gain units)             */
+    double T1;          /* inversion relaxation time (round trips)            */
+    double mod_amp;     /* pump modulation depth (0 = uniform pump)            */
+    double mod_period;  /* pump modulation period d (m); 0 = uniform          */
+} orc_params;
+
+/* One-dimensional DFT of length n = 2^a 3^b, in place, unnormalized.
+ * inverse = 0: X[k] = sum_j x[j] exp(-2 pi i jk/n); inverse = 1: exp(+...). */
+int  orc_fft1d(double* x, int n, int inverse);
+
+/* The same transform evaluated by the O(n^2) definition. */
+int  orc_dft_brute1d(const double* in, double* out, int n, int inverse);
+
+/* Two-dimensional transform of an n x n row-major array: all rows, then all
+ * columns.  Unnormalized in both directions. */
+int  orc_fft2(double* x, int n, int inverse);
+
+/* The same 2D transform evaluated by the O(n^4) definition. */
+int  orc_dft_brute2d(const double* in, double* out, int n, int inverse);
+
+/* Advance (E, Ninv) by n_trips iterates of the round-trip map.
+ * E: N*N complex field at the gain-sheet plane, before the local step.
+ * Ninv: N*N inversion.  Both are updated in place.
+ * trace (nullable): 4*n_trips doubles; for trip t the raw sums
+ *   [4t+0] S1 = sum |E_t|^2
+ *   [4t+1] S2 = sum |A|^2 |E_t|^2
+ *   [4t+2] S3 = sum |A|^2 exp(N_t) |E_t|^2
+ *   [4t+3] S4 = sum N_t
+ * taken over the grid in row-major order.
+ * Returns 0, or -1 on invalid parameters / allocation failure. */
+int  orc_run(const orc_params* p, double* E, double* Ninv, int n_trips,
+             double* trace);
+
+/* Number of radial bins of the far-field spectrum for an N-point grid. */
+int  orc_nbins(int N);
+
+/* Far-field radial spectrum of the field leaving the gain sheet:
+ * radial[k] = sum over (p,q) with round(sqrt(p~^2 + q~^2)) = k of |FFT2(G)|^2,
+ * G = sqrt(R) A exp(N/2) E.  radial has nbins >= orc_nbins(N) entries.
+ * Returns the dominant bin (argmax over k >= 1, lowest on ties) or -1. */
+int  orc_spectrum(const orc_params* p, const double* E, const double* Ninv,
+                  double* radial, int nbins);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,363 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these compare the oracle with itself: each checks it against a
+definition written out independently (brute-force DFT), a library routine
+(numpy.fft), a closed form the paper prints or that follows from it
+(Gaussian-beam propagation, Talbot self-imaging, the Gaussian-aperture
+eigenvalue, the plane-wave saturated steady state, the relaxation-oscillation
+time), or an invariant (Parseval, energy balance, mirror symmetry).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import CavityParams
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def rand_c(shape, seed):
+    r = np.random.default_rng(seed)
+    return r.standard_normal(shape) + 1j * r.standard_normal(shape)
+
+
+def grid(n, dx):
+    x = (np.arange(n) - n / 2) * dx
+    return np.meshgrid(x, x, indexing="xy")  # X[y, x], Y[y, x]
+
+
+def passive(n, dx, lam, L, **kw):
+    """Gain switched off: R = 1, N = N0 = 0, so only the aperture and the
+    propagation act."""
+    d = dict(N=n, dx=dx, lam=lam, L=L, R=1.0, N0=0.0, T1=1.0, ap_kind=0)
+    d.update(kw)
+    return CavityParams(**d)
+
+
+# ---------------------------------------------------------------- FFT ----
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 96, 128])
+@pytest.mark.parametrize("inverse", [False, True])
+def test_fft1d_matches_brute_dft(n, inverse):
+    x = rand_c(n, n)
+    got = oracle.fft1d(x, inverse)
+    ref = oracle.dft_brute1d(x, inverse)
+    assert rel(got, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 8, 12, 16, 24, 32])
+def test_fft2_matches_brute_dft(n):
+    x = rand_c((n, n), 100 + n)
+    assert rel(oracle.fft2(x), oracle.dft_brute2d(x)) <= 1e-13
+    assert rel(oracle.fft2(x, True), oracle.dft_brute2d(x, True)) <= 1e-13
+
+
+def test_brute_dft_definition_on_delta_and_plane_wave():
+    # DFT of a unit impulse at j0 is exp(-2 pi i k j0 / n); of a plane wave
+    # exp(2 pi i k0 j / n) it is n at k0 and zero elsewhere.
+    n = 12
+    d = np.zeros(n, complex)
+    d[5] = 1.0
+    k = np.arange(n)
+    assert np.allclose(oracle.dft_brute1d(d), np.exp(-2j * np.pi * k * 5 / n), atol=1e-14)
+    pw = np.exp(2j * np.pi * 7 * k / n)
+    want = np.zeros(n, complex)
+    want[7] = n
+    assert np.allclose(oracle.dft_brute1d(pw), want, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [256, 384, 512, 768, 1024])
+def test_fft1d_matches_numpy(n):
+    x = rand_c(n, 7 * n)
+    assert rel(oracle.fft1d(x), np.fft.fft(x)) <= 1e-13
+    assert rel(oracle.fft1d(x, True), np.fft.ifft(x) * n) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [64, 96, 256])
+def test_fft2_matches_numpy_and_roundtrips(n):
+    x = rand_c((n, n), 3 * n)
+    f = oracle.fft2(x)
+    assert rel(f, np.fft.fft2(x)) <= 1e-13
+    assert rel(oracle.fft2(f, True) / (n * n), x) <= 1e-13
+
+
+def test_fft_rejects_unsupported_length():
+    with pytest.raises(ValueError):
+        oracle.fft1d(np.ones(10, complex))
+
+
+# ------------------------------------------------------- propagation ----
+
+def test_propagation_is_unitary_parseval():
+    """|H| = 1: with gain, mirror and aperture off the diffraction step keeps
+    sum |E|^2 (transfer function of the operator exponent, Sec. 2.3 Eq. (25))."""
+    n, dx = 128, 1e-5
+    p = passive(n, dx, 1.064e-6, 2e-3)
+    e0 = rand_c((n, n), 11)
+    e, _, tr = oracle.run(p, e0, np.zeros((n, n)), 6)
+    s = [np.sum(np.abs(e0) ** 2)] + list(tr[1:, 0]) + [np.sum(np.abs(e) ** 2)]
+    s = np.asarray(s)
+    assert np.max(np.abs(s / s[0] - 1.0)) <= 1e-13
+
+
+@pytest.mark.parametrize("focal_over_L", [math.inf, 3.0, -5.0])
+def test_gaussian_beam_closed_form(focal_over_L):
+    """Sec. 3, Eqs. (27)-(28): a Gaussian of width D_a passing a mirror of
+    focal length F and propagating over L carries the envelope factor
+    q = 1 + i/N_f + L/F, N_f = k D_a^2 / L:  E = exp(-c r^2 / q) / q with
+    c = 1/(2 D_a^2) - i k/(2F) (for a flat mirror c = 1/(2 D_a^2), the form
+    printed in Eq. (27)).  The oracle applies the Gaussian aperture with the
+    curvature phase to a uniform field and propagates once."""
+    n = 256
+    lam, L = 1.064e-6, 2e-3
+    a = math.sqrt(100 * lam * L)          # Fresnel number 100
+    dx = 2 * a / n
+    Da = 0.07 * a
+    F = focal_over_L * L
+    p = passive(n, dx, lam, L, ap_kind=2, ap_radius=Da, focal=F)
+    e, _, _ = oracle.run(p, np.ones((n, n)), np.zeros((n, n)), 1)
+    X, Y = grid(n, dx)
+    r2 = X ** 2 + Y ** 2
+    k = 2 * math.pi / lam
+    Nf = k * Da ** 2 / L
+    q = 1 + 1j / Nf + (0.0 if math.isinf(F) else L / F)
+    c = 1 / (2 * Da ** 2) - (0.0 if math.isinf(F) else 1j * k / (2 * F))
+    want = np.exp(-c * r2 / q) / q
+    assert rel(e, want) <= 1e-12
+
+
+def _talbot_field(n, M, seed):
+    """Random field whose spectrum sits on multiples of M (period N/M samples)."""
+    r = np.random.default_rng(seed)
+    spec = np.zeros((n, n), complex)
+    idx = np.arange(-3, 4) * M % n
+    for iy in idx:
+        for ix in idx:
+            spec[iy, ix] = r.standard_normal() + 1j * r.standard_normal()
+    return np.fft.ifft2(spec) * n * n
+
+
+@pytest.mark.parametrize("n,M", [(256, 16), (384, 12)])
+def test_talbot_self_imaging(n, M):
+    """Intro and Sec. 3: a field of period d reproduces itself after the
+    Talbot length z_T = 2 d^2/lambda, and after z_T/2 it reappears shifted by
+    d/2 in x and y (the half-Talbot shift of Sec. 5)."""
+    lam = 1.064e-6
+    dx = 2e-6
+    d = n * dx / M
+    zT = 2 * d ** 2 / lam
+    e0 = _talbot_field(n, M, 5)
+    e1, _, _ = oracle.run(passive(n, dx, lam, zT), e0, np.zeros((n, n)), 1)
+    assert rel(e1, e0) <= 1e-13
+    eh, _, _ = oracle.run(passive(n, dx, lam, zT / 2), e0, np.zeros((n, n)), 1)
+    half = n // (2 * M)
+    assert rel(eh, np.roll(np.roll(e0, half, 0), half, 1)) <= 1e-13
+    # and a generic length does not self-image
+    eg, _, _ = oracle.run(passive(n, dx, lam, 0.37 * zT), e0, np.zeros((n, n)), 1)
+    assert rel(eg, e0) > 1e-2
+
+
+def test_gaussian_aperture_eigenvalue():
+    """Sec. 3, Eq. (26): with a Gaussian aperture exp(-r^2/(2 D_a^2)) the map
+    has exact Gaussian eigenfunctions.  Writing the mode as exp(-g r^2) and
+    u = beta + g, beta = 1/(2 D_a^2), kappa = lambda L / pi, the propagation
+    law of the previous test gives u^2 - beta u + i beta/kappa = 0 and the
+    round-trip eigenvalue mu = 1/(1 + i kappa u).  Power iteration with the
+    oracle must converge to mu and to the mode shape."""
+    n = 256
+    lam, L = 1.064e-6, 2e-3
+    a = math.sqrt(100 * lam * L)
+    dx = 2 * a / n
+    Da = 0.2 * a
+    p = passive(n, dx, lam, L, ap_kind=2, ap_radius=Da)
+    beta = 1 / (2 * Da ** 2)
+    kappa = lam * L / math.pi
+    disc = np.sqrt(beta ** 2 - 4j * beta / kappa + 0j)
+    roots = [(beta + disc) / 2, (beta - disc) / 2]
+    u = [z for z in roots if (z - beta).real > 0][0]
+    mu = 1 / (1 + 1j * kappa * u)
+    X, Y = grid(n, dx)
+    e = np.exp(-(X ** 2 + Y ** 2) / (0.5 * Da) ** 2).astype(complex)
+    for _ in range(8):
+        e, _, _ = oracle.run(p, e, np.zeros((n, n)), 25)
+        e /= e[n // 2, n // 2]
+    e_next, _, _ = oracle.run(p, e, np.zeros((n, n)), 1)
+    ratio = e_next[n // 2, n // 2] / e[n // 2, n // 2]
+    assert abs(ratio - mu) <= 1e-10
+    mode = np.exp(-(u - beta) * (X ** 2 + Y ** 2))
+    assert rel(e, mode) <= 1e-9
+
+
+# ------------------------------------------------------- gain sheet -----
+
+def test_plane_wave_saturated_fixed_point():
+    """Eq. (1) with Eq. (6): a uniform plane wave on a uniform pump N0 = r ln(1/R)
+    with no aperture has the exact fixed point N* = ln(1/R) (gain balances the
+    mirror) and |E*|^2 = (r - 1)/T1 (relaxation balances depletion); the
+    transform only touches the DC term, where H = 1."""
+    n, R, r, T1 = 16, 0.9, 2.0, 1000.0
+    Nth = math.log(1 / R)
+    p = CavityParams(N=n, dx=1e-5, lam=1.064e-6, L=2e-3, R=R, N0=r * Nth, T1=T1, ap_kind=0)
+    I = (r - 1) / T1
+    e0 = np.full((n, n), math.sqrt(I) * np.exp(0.3j))
+    n0 = np.full((n, n), Nth)
+    e, ninv, tr = oracle.run(p, e0, n0, 1000)
+    assert np.max(np.abs(e - e0)) / math.sqrt(I) <= 1e-12
+    assert np.max(np.abs(ninv - Nth)) / Nth <= 1e-12
+    assert np.allclose(tr[:, 0], I * n * n, rtol=1e-12)
+
+
+def test_plane_wave_threshold():
+    """Below threshold (r < 1) a plane wave decays, above it grows: the
+    round-trip intensity factor is R exp(N0)."""
+    n, R, T1 = 8, 0.9, 1000.0
+    Nth = math.log(1 / R)
+    for r, grows in [(0.8, False), (1.3, True)]:
+        p = CavityParams(N=n, dx=1e-5, lam=1.064e-6, L=2e-3, R=R, N0=r * Nth, T1=T1, ap_kind=0)
+        e0 = np.full((n, n), 1e-4 + 0j)
+        e, _, _ = oracle.run(p, e0, np.full((n, n), r * Nth), 50)
+        assert (abs(e[0, 0]) > 1e-4) == grows
+        want = 1e-4 * (R * math.exp(r * Nth)) ** 25   # amplitude: sqrt per trip
+        assert abs(abs(e[0, 0]) - want) / want <= 1e-3   # depletion 1e-8 per trip
+
+
+def test_relaxation_oscillation_frequency():
+    """Sec. 2.1, Eq. (7): near the steady state the intensity rings at the
+    relaxation-oscillation time tau_rel = sqrt(T1 tau_c)/sqrt(sigma N0 c tau_c - 1).
+    In round-trip units tau_c = 1/ln(1/R) and sigma N0 c tau_c = r, so
+    omega = sqrt(ln(1/R)(r - 1)/T1) rad per trip (small-signal limit).  The
+    discrete map's linearisation has the exact rotation angle
+    atan2(sqrt(N* I* - e^2/4), 1 - e/2), e = r/T1."""
+    n, R, r, T1 = 8, 0.9, 2.0, 1000.0
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as f:
+        gold = json.load(f)["plain_256_relaxation"]
+    Nth = math.log(1 / R)
+    p = CavityParams(N=n, dx=1e-5, lam=1.064e-6, L=2e-3, R=R, N0=r * Nth, T1=T1, ap_kind=0)
+    I = (r - 1) / T1
+    e0 = np.full((n, n), math.sqrt(I * (1 + 1e-4)) + 0j)
+    _, _, tr = oracle.run(p, e0, np.full((n, n), Nth), 4000)
+    s = tr[:, 0] / (n * n) - I
+    # zero crossings -> mean half period
+    zc = np.where(np.signbit(s[:-1]) != np.signbit(s[1:]))[0]
+    # interpolate crossing positions
+    xs = zc + s[zc] / (s[zc] - s[zc + 1])
+    half_period = np.mean(np.diff(xs))
+    omega_meas = math.pi / half_period
+    e = r / T1
+    omega_exact = math.atan2(math.sqrt(Nth * I - e * e / 4), 1 - e / 2)
+    omega_paper = math.sqrt(Nth * (r - 1) / T1)
+    assert abs(omega_meas - omega_exact) / omega_exact <= 2e-3
+    assert abs(omega_meas - omega_paper) / omega_paper <= 1e-2
+    assert abs(half_period - gold["half_period_trips"]) <= gold["half_period_tol"]
+
+
+# ------------------------------------------------- invariants -----------
+
+def _c1(n=64):
+    lam, L, F = 1.064e-6, 2e-3, 30.0
+    a = math.sqrt(F * lam * L)
+    R = 0.9
+    return CavityParams(N=n, dx=2 * a / n, lam=lam, L=L, R=R, N0=2 * math.log(1 / R),
+                        T1=1000.0, ap_kind=1, ap_radius=0.8 * a, ap_order=10)
+
+
+def test_energy_balance_identity():
+    """Parseval after the local step: W_{n+1} = R sum |A|^2 e^{N_n} |E_n|^2,
+    i.e. next energy = gain - aperture loss - output (all from the trace)."""
+    p = _c1()
+    n = p.N
+    e0 = rand_c((n, n), 3) * 1e-2
+    _, _, tr = oracle.run(p, e0, np.full((n, n), p.N0), 40)
+    s1, s2, s3 = tr[:, 0], tr[:, 1], tr[:, 2]
+    assert np.allclose(s1[1:], p.R * s3[:-1], rtol=1e-12)
+    gain, loss, out = s3 - s2, s1 - s2, (1 - p.R) * s3
+    assert np.allclose(s1[1:] - s1[:-1], (gain - loss - out)[:-1], rtol=1e-9, atol=1e-15 * s1.max())
+
+
+def test_inversion_update_pointwise():
+    """The second line of Eq. (1) read as the forward-Euler step of Eq. (6):
+    N_{n+1} = N_n + (N0 - N_n)/T1 - N_n |E_n|^2, pointwise, with a
+    modulated pump N0 (1 + m cos(2 pi x/d) cos(2 pi y/d))."""
+    n = 32
+    p = _c1(n)
+    p.mod_amp, p.mod_period = 0.3, p.N * p.dx / 4
+    e0 = rand_c((n, n), 9) * 0.3
+    n_in = 0.1 + 0.05 * np.random.default_rng(2).standard_normal((n, n))
+    _, n1, tr = oracle.run(p, e0, n_in, 1)
+    X, Y = grid(n, p.dx)
+    pump = p.N0 * (1 + 0.3 * np.cos(2 * np.pi * X / p.mod_period) * np.cos(2 * np.pi * Y / p.mod_period))
+    want = n_in + (pump - n_in) / p.T1 - n_in * np.abs(e0) ** 2
+    assert np.max(np.abs(n1 - want)) <= 1e-15
+    assert abs(tr[0, 3] - n_in.sum()) <= 1e-12 * abs(n_in.sum())
+
+
+def test_mirror_and_transpose_symmetry():
+    """Symmetric aperture, pump and initial field stay symmetric under
+    x -> -x, y -> -y and x <-> y (index j -> (N - j) mod N)."""
+    p = _c1(64)
+    n = p.N
+    e = rand_c((n, n), 4) * 1e-2
+    flip = lambda z: np.roll(z[::-1], 1, axis=0)
+    e = e + flip(e)
+    e = e + flip(e.T).T
+    e = e + e.T
+    e, ninv, _ = oracle.run(p, e, np.full((n, n), p.N0), 20)
+    nrm = np.linalg.norm(e)
+    assert np.linalg.norm(e - flip(e)) / nrm <= 1e-12
+    assert np.linalg.norm(e - flip(e.T).T) / nrm <= 1e-12
+    assert np.linalg.norm(e - e.T) / nrm <= 1e-12
+    assert np.max(np.abs(ninv - ninv.T)) <= 1e-14
+
+
+def test_one_trip_matches_numpy_split_step():
+    """One iterate written with numpy.fft (a library routine for both
+    transforms), the transfer function built from the Gaussian-beam-pinned
+    phase, and the local step of Eq. (1)."""
+    p = _c1(48)
+    n = p.N
+    e0 = rand_c((n, n), 8) * 0.05
+    n0 = np.full((n, n), p.N0) + 0.01 * np.random.default_rng(1).standard_normal((n, n))
+    e1, n1, _ = oracle.run(p, e0, n0, 1)
+    X, Y = grid(n, p.dx)
+    A = np.exp(-((X ** 2 + Y ** 2) / p.ap_radius ** 2) ** 5)
+    G = math.sqrt(p.R) * A * np.exp(n0 / 2) * e0
+    f = np.fft.fftfreq(n, p.dx)
+    FX, FY = np.meshgrid(f, f, indexing="xy")
+    H = np.exp(-1j * np.pi * p.lam * p.L * (FX ** 2 + FY ** 2))
+    assert rel(e1, np.fft.ifft2(H * np.fft.fft2(G))) <= 1e-13
+
+
+# --------------------------------------------------------- spectrum -----
+
+def test_spectrum_of_tilted_plane_wave():
+    """A plane wave with integer wave numbers (3, 4) puts all far-field power
+    in radial bin 5; total power obeys Parseval (sum |FFT2 G|^2 = N^2 sum |G|^2)."""
+    n = 64
+    p = CavityParams(N=n, dx=1e-5, lam=1.064e-6, L=2e-3, R=0.81, N0=0.0, T1=100.0, ap_kind=0)
+    j = np.arange(n)
+    X, Y = np.meshgrid(j, j, indexing="xy")
+    e = np.exp(2j * np.pi * (3 * X + 4 * Y) / n)
+    radial, k = oracle.spectrum(p, e, np.zeros((n, n)))
+    assert k == 5
+    assert radial.size == oracle.nbins(n) == int(round(n / math.sqrt(2))) + 1
+    assert abs(radial[5] - n ** 4 * 0.81) <= 1e-9 * n ** 4
+    assert abs(radial.sum() - radial[5]) <= 1e-9 * n ** 4
+
+
+def test_spectrum_dc_is_excluded_from_the_dominant_bin():
+    n = 32
+    p = CavityParams(N=n, dx=1e-5, lam=1.064e-6, L=2e-3, R=1.0, N0=0.0, T1=100.0, ap_kind=0)
+    j = np.arange(n)
+    X, Y = np.meshgrid(j, j, indexing="xy")
+    e = 10 + np.exp(2j * np.pi * 2 * X / n) + 0.5 * np.exp(2j * np.pi * 7 * Y / n)
+    radial, k = oracle.spectrum(p, e, np.zeros((n, n)))
+    assert radial[0] > radial[2]
+    assert k == 2
