@@ -1,0 +1,232 @@
+/*
+ * lsr.h -- split-step round-trip map of a microchip-laser cavity on one
+ * AMD Instinct MI355X (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * The method (Okulov, "Two-dimensional periodic and quasiperiodic spatial
+ * structures in microchip laser resonator"): the intracavity field E(x,y)
+ * on an N x N grid is carried bounce by bounce through the cavity map of the
+ * Introduction, Eq. (1), in the form of Sec. 2.2, Eq. (11): a local step
+ * (gain sheet whose inversion N(x,y) is frozen during the pass, mirror
+ * reflectivity R, aperture D of Eq. (12)) followed by Fresnel diffraction over
+ * the cavity length L, applied in Fourier space as the operator exponent
+ * exp[i L/(2k) Laplacian] of Sec. 2.3, Eq. (25).  The inversion then relaxes
+ * toward the pump and is depleted by |E|^2 (Eq. (1), second line, read as
+ * the one-round-trip forward-Euler step of the B-class rate equation,
+ * Eq. (6)).  One round trip n -> n+1, with sigma = 1:
+ *
+ *     I      = |E_n|^2
+ *     G      = sqrt(R) A(x,y) exp(N_n/2) E_n            (local step)
+ *     N_{n+1}= N_n + (N0(x,y) - N_n)/T1 - N_n I          (inversion update)
+ *     E_{n+1}= IFFT2( H . FFT2(G) ),
+ *              H = exp(-i pi lambda L (fx^2 + fy^2))     (diffraction)
+ *
+ * Grid: x_j = (j - N/2) dx, row-major (row y, column x) at index y*N + x;
+ * fx = p~/(N dx) with the signed index p~ = p (p < N/2) else p - N.
+ * Forward FFT unnormalized, inverse scaled by 1/N^2.
+ *
+ * Error behaviour: every entry point returns an lsr_status (0 = success);
+ * nothing throws across the ABI.  lsr_last_error() gives a thread-local
+ * message for the last failure on the calling thread.  GPU work is enqueued
+ * asynchronously on the plan's stream: launch failures are reported by the
+ * call, faults and non-finite state by the next synchronising call
+ * (lsr_sync, lsr_diag, lsr_trace).
+ *
+ * Ownership: the caller owns E and Ninv (device memory, borrowed for the
+ * duration of a call).  A plan owns its tables, scratch, trace ring and
+ * graphs; a batch owns its task tables and counters but only borrows its
+ * plans, which must outlive it.
+ */
+#ifndef LSR_H
+#define LSR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lsr_plan_s*  lsr_plan;
+typedef struct lsr_batch_s* lsr_batch;
+
+typedef enum {
+    LSR_OK           =  0,
+    LSR_EINVAL       = -1,   /* bad argument                                  */
+    LSR_ENOMEM       = -2,   /* device or host allocation failed              */
+    LSR_EDEVICE      = -3,   /* HIP runtime error (launch, copy, sync)        */
+    LSR_EUNSUPPORTED = -4,   /* grid size or mode not compiled in             */
+    LSR_ENONFINITE   = -5    /* the state became NaN/Inf (trip in message)    */
+} lsr_status;
+
+/* Arithmetic form of a plan.
+ * PLAIN:     complex FP32 field and FFTs; twiddles and the propagator phase
+ *            pi lambda L (fx^2+fy^2) generated in FP32 arithmetic; the
+ *            per-lane diagnostics sums in FP32.
+ * FP64TAB:   complex FP32 field and FFTs; twiddles and the propagator phase
+ *            generated in FP64 and reduced modulo one turn before rounding
+ *            to FP32; the propagator is the separable product hx(p) hx(q);
+ *            diagnostics sums in FP64.
+ * FP64:      the whole map in FP64 (validation form); E is complex128 and
+ *            Ninv is double. */
+typedef enum { LSR_PREC_PLAIN = 0, LSR_PREC_FP64TAB = 1, LSR_PREC_FP64 = 2 } lsr_prec;
+
+/* Aperture modulus D0 of Eq. (12) (finite width of gain medium / mirror). */
+typedef enum {
+    LSR_AP_NONE = 0,         /* D0 = 1                                        */
+    LSR_AP_SUPERGAUSS = 1,   /* D0 = exp(-(r/radius)^order), order even >= 2  */
+    LSR_AP_GAUSS = 2,        /* D0 = exp(-r^2/(2 radius^2)), Eq. (26)         */
+    LSR_AP_MASK = 3          /* D0 = mask[y*N + x]                             */
+} lsr_aperture_kind;
+
+typedef struct {
+    int          kind;       /* lsr_aperture_kind                             */
+    double       radius;     /* m                                             */
+    int          order;      /* super-Gaussian exponent on r                  */
+    const void*  mask;       /* kind 3: device float (double for FP64 plans)
+                                N*N amplitude, borrowed for the plan's life   */
+} lsr_aperture;
+
+/* Diagnostics of one state (E_n, N_n), all sums taken in FP64:
+ *   energy        W   = dx^2 sum |E|^2
+ *   power_out     P   = (1-R) dx^2 sum |A|^2 e^N |E|^2  (leaves through the mirror)
+ *   gain_sum          = dx^2 sum |A|^2 (e^N - 1) |E|^2  (added by the gain sheet)
+ *   aperture_loss     = dx^2 sum (1 - |A|^2) |E|^2
+ *   inv_sum           = dx^2 sum N
+ * and the far-field radial spectrum of G = sqrt(R) A e^{N/2} E:
+ *   radial[k] = sum over round(sqrt(p~^2 + q~^2)) = k of |FFT2(G)(p,q)|^2,
+ *   k = 0 .. nbins-1, nbins = round(N/sqrt(2)) + 1;
+ *   dominant_bin = argmax over k >= 1 (lowest on ties). */
+typedef struct {
+    double  energy, power_out, gain_sum, aperture_loss, inv_sum;
+    int     dominant_bin;
+    int     nbins;           /* out: number of bins of this plan               */
+    double* radial;          /* in: host buffer of >= nbins doubles, or NULL   */
+} lsr_diag_out;
+
+/* Create a plan for one cavity.
+ * N      grid points per side; supported: 256, 384, 512, 768, 1024, 2048, 4096
+ *        (LSR_EUNSUPPORTED otherwise; FP64 plans up to 2048).
+ * dx     grid spacing (m) > 0; lambda wavelength (m) > 0; L propagation length
+ *        of one iterate (m) >= 0.  The Fresnel number is (N dx/2)^2/(lambda L).
+ * F      mirror focal length (m) of the curvature phase exp(i k r^2/(2F)) of
+ *        Eq. (12); 0 or +-INFINITY = flat mirror.
+ * R      mirror reflectivity, 0 < R <= 1.
+ * ap     aperture (NULL = LSR_AP_NONE).
+ * The gain defaults to N0 = 0, T1 = 1 (set it with lsr_plan_set_gain), the
+ * stream to the null stream.  Tables are built in FP64 on the host and
+ * uploaded once; no allocation happens in later calls except lsr_diag's
+ * first use of its spectrum scratch. */
+int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L,
+                    double F, double R, const lsr_aperture* ap, lsr_prec prec);
+
+/* Pump and relaxation (Eq. (1), second line; periodic pump of Sec. 3):
+ * N0(x,y) = N0 (1 + mod_amp cos(2 pi x/mod_period) cos(2 pi y/mod_period)),
+ * uniform when mod_amp = 0 or mod_period = 0.  T1 > 0 in round trips. */
+int lsr_plan_set_gain(lsr_plan p, double N0, double T1, double mod_amp,
+                      double mod_period);
+
+/* Bind the plan to a HIP stream (hipStream_t passed as void*; NULL = null
+ * stream).  All later work of the plan is enqueued on it. */
+int lsr_plan_set_stream(lsr_plan p, void* hip_stream);
+
+/* Advance the state n_trips >= 0 round trips, in place, asynchronously.
+ * E    device complex64 (complex128 for FP64 plans) N*N, row-major, the field
+ *      at the gain sheet before the local step (E_n in, E_{n+n_trips} out).
+ * Ninv device float (double for FP64 plans) N*N, row-major (N_n in, out).
+ * Both must be 16-byte aligned and must not overlap.  During the call E's
+ * memory also holds the transformed field in an internal tiled layout; it is
+ * row-major again when the enqueued work completes.  Launches: 2 per trip
+ * plus 1.  The per-trip diagnostics sums go to the plan's trace ring. */
+int lsr_roundtrips(lsr_plan p, void* E, void* Ninv, int n_trips);
+
+/* Wait for the plan's stream; LSR_ENONFINITE if any trip of the calls since
+ * the last lsr_sync/lsr_trace saw a non-finite state. */
+int lsr_sync(lsr_plan p);
+
+/* Copy the raw per-trip sums of the last lsr_roundtrips call (oldest first)
+ * to host memory: out[4t+0..3] = S1 = sum|E|^2, S2 = sum|A|^2|E|^2,
+ * S3 = sum|A|^2 e^N |E|^2, S4 = sum N of the incoming state of trip t.
+ * Copies min(capacity, n_trips of that call, ring size) records; returns the
+ * count (>= 0) or a negative status.  Synchronises the stream. */
+int lsr_trace(lsr_plan p, double* out, int capacity);
+
+/* Diagnostics of the state (E, Ninv); synchronises the stream. */
+int lsr_diag(lsr_plan p, const void* E, const void* Ninv, lsr_diag_out* out);
+
+/* Number of radial spectrum bins of a plan (round(N/sqrt(2)) + 1). */
+int lsr_plan_nbins(lsr_plan p);
+
+void lsr_plan_destroy(lsr_plan p);
+
+/* ---------------------------------------------------------------------- */
+/* Batching: many cavities of uneven N and parameters advanced together by */
+/* one persistent kernel per round trip, replayed as a HIP graph of k      */
+/* round trips.  Only FP32 plans (PLAIN / FP64TAB) can be batched.         */
+/* ---------------------------------------------------------------------- */
+
+/* Build a batch over count >= 1 plans (borrowed).  The task table, the
+ * launch shape and k come from the autotune cache when it holds an entry
+ * for this mix of sizes, else from built-in defaults.  The batch runs on
+ * the stream of plans[0]. */
+int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count);
+
+/* Advance cavity i's state (E[i], Ninv[i], laid out as for lsr_roundtrips)
+ * by n_trips round trips, all cavities together, asynchronously.  The
+ * per-trip sums go to each plan's trace ring. */
+int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* Ninv, int n_trips);
+
+/* Diagnostics of cavity idx of the batch; same as lsr_diag on its plan. */
+int lsr_batch_diag(lsr_batch b, int idx, const void* E, const void* Ninv,
+                   lsr_diag_out* out);
+
+/* Set the trips per captured graph (k >= 1; 0 = no graph, eager launches). */
+int lsr_batch_set_graph_trips(lsr_batch b, int k);
+
+void lsr_batch_destroy(lsr_batch b);
+
+/* Autotune: time the candidate launch shapes of plan p (and/or of batch b)
+ * on the device with scratch state, keep the fastest, and store it in the
+ * JSON cache at cache_path (NULL = $LSR_TUNE_CACHE or no file).  The winner
+ * applies to the plan/batch at once and to later plans/batches of the same
+ * sizes and precision.  Synchronises. */
+int lsr_autotune(lsr_plan p, lsr_batch b, const char* cache_path);
+
+/* ---------------------------------------------------------------------- */
+/* Host-side introspection (no GPU needed).                                 */
+/* ---------------------------------------------------------------------- */
+
+const char* lsr_last_error(void);
+const char* lsr_version(void);
+
+/* Whether grid size N is compiled in for prec (1) or not (0). */
+int lsr_supported(int N, int prec);
+
+/* The FFT factorisation used for N: writes up to max radices (forward pass
+ * order) to radices and returns their count, lanes per line and lines per
+ * workgroup; negative status if N is unsupported. */
+int lsr_fft_shape(int N, int prec, int* radices, int max, int* lanes_per_line,
+                  int* lines_per_group);
+
+/* The FP64-built per-axis propagator table of an FP64TAB plan:
+ * out[2p], out[2p+1] = Re, Im of hx(p) = exp(-i pi lambda L fx_p^2) / N,
+ * the phase reduced modulo one turn in FP64 before rounding; p = 0..N-1.
+ * Pure host arithmetic, for inspection and tests. */
+int lsr_propagator_table(int N, double dx, double lambda, double L, float* out);
+
+/* The Stockham twiddle tables of grid size N (forward then inverse passes,
+ * concatenated; per pass with sub-length Ns > 1 and radix R, Ns*R entries
+ * w[k*R + r] = exp(-+2 pi i r k/(Ns R))), as interleaved floats built in FP64
+ * (prec FP64TAB) or in FP32 arithmetic (PLAIN).  Returns the number of
+ * complex entries, or the required count if out is NULL. */
+int lsr_twiddle_table(int N, int prec, float* out, int capacity);
+
+/* The batch packer's task order for a set of grid sizes, host only:
+ * writes per task (cavity index, kind 0 = row block / 1 = column block,
+ * block index) triples to tasks (3 ints each) and returns the task count;
+ * with tasks = NULL returns the count only.  lag = number of cavities whose
+ * row tasks precede the column tasks of a cavity (-1 = default). */
+int lsr_pack_tasks(const int* sizes, int count, int lag, int* tasks, int capacity);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSR_H */

@@ -1,0 +1,72 @@
+// cx.hpp -- complex arithmetic in registers and compile-time trigonometry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <type_traits>
+#include <utility>
+
+namespace lsr {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+
+// a * (DIR * i): DIR = -1 gives -i (forward quarter turn), +1 gives +i.
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> rot_q(cx<T> a) {
+    if constexpr (DIR > 0) return {-a.im, a.re};
+    else return {a.im, -a.re};
+}
+
+// Compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+// Compile-time sin/cos (Taylor series after reduction to [-pi, pi]); used
+// only for the constant twiddles inside the small register DFTs.
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double ce_reduce(double x) {
+    while (x > kPi) x -= 2.0 * kPi;
+    while (x < -kPi) x += 2.0 * kPi;
+    return x;
+}
+constexpr double ce_sin(double x) {
+    x = ce_reduce(x);
+    double term = x, sum = x;
+    for (int n = 1; n < 40; ++n) {
+        term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+constexpr double ce_cos(double x) {
+    x = ce_reduce(x);
+    double term = 1.0, sum = 1.0;
+    for (int n = 1; n < 40; ++n) {
+        term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+        sum += term;
+    }
+    return sum;
+}
+
+}  // namespace lsr

@@ -1,0 +1,52 @@
+// desc.hpp -- per-cavity descriptor read by the kernels (host and device).
+#pragma once
+
+#include <cstdint>
+
+namespace lsr {
+
+enum Prec : int { PREC_PLAIN = 0, PREC_FP64TAB = 1, PREC_FP64 = 2 };
+enum ApKind : int { AP_NONE = 0, AP_SUPERGAUSS = 1, AP_GAUSS = 2, AP_MASK = 3 };
+
+// Row-pass modes.  FIRST reads the row-major state, MID the tiled transform
+// of the previous trip, LAST finishes the inverse transform and writes the
+// row-major state, DIAG evaluates the local step and forward row transform
+// of a state into scratch without touching the state.
+enum RowMode : int { ROW_FIRST = 0, ROW_MID = 1, ROW_LAST = 2, ROW_DIAG = 3 };
+enum ColMode : int { COL_PROP = 0, COL_DIAG = 1 };
+
+// Counters of a cavity (device, 16 words):
+//  [0] trips completed (trace ring slot of the next trip)
+//  [1] first trip (1-based) whose sums were non-finite, 0 if none
+enum : int { CNT_TRIPS = 0, CNT_NONFINITE = 1, CNT_WORDS = 16 };
+
+struct CavDesc {
+    void* E;                // field (row-major between calls, tiled inside)
+    void* Ninv;             // inversion, row-major
+    const void* tw;         // Stockham twiddles of this N (forward, then inverse passes)
+    const void* hx;         // per-axis propagator hx(p) (FP64TAB / FP64), N entries
+    const void* pump_c;     // cos(2 pi x_i / d), N entries, or null (uniform pump)
+    const void* foc;        // exp(i pi x_i^2/(lambda F)), N complex entries, or null (flat mirror)
+    const void* mask;       // N*N aperture amplitude (AP_MASK) or null
+    void* scratch;          // DIAG: tiled forward row transform of G (N*N complex)
+    double* partials;       // per row block: 4 sums
+    double* radial_part;    // DIAG: per column block radial spectrum partials
+    double* trace;          // ring of trace_cap records of 4 sums
+    unsigned* counters;     // CNT_WORDS words
+    int N;
+    int prec;
+    int ap_kind;
+    int ap_half_order;      // super-Gaussian exponent / 2
+    int trace_cap;
+    int nrb;                // row blocks = column blocks = N / LPW
+    int nbins;
+    int pad_;
+    double sqrtR;
+    double N0, inv_T1, mod_amp;
+    double dx;
+    double inv_r0sq;        // 1/r0^2 (super-Gaussian), 1/(2 r0^2) (Gaussian)
+    double phase_c;         // PLAIN: pi lambda L / (N dx)^2, rad per index^2
+    double inv_nn;          // 1/N^2
+};
+
+}  // namespace lsr

@@ -1,0 +1,236 @@
+// fft.hpp -- per-line Stockham FFT held in registers, exchanged through LDS.
+//
+// The nonlocal step of the cavity map (paper, Sec. 2.2, Eq. (11), evaluated
+// as the operator exponent of Sec. 2.3, Eq. (25)) is diagonal in Fourier
+// space; the split-step method (abstract; Sec. 2.2) reaches Fourier space
+// with 2D DFTs.  Each 1D DFT of length N = R_0 R_1 ... R_{NP-1} runs as NP
+// Stockham autosort passes.  Pass s (radix R, sub-length Ns = R_0...R_{s-1})
+// takes butterfly j in [0, N/R):
+//     x_r   = in[j + r N/R]                      r = 0..R-1
+//     x_r  *= w^{r k},  k = j mod Ns,  w = exp(DIR 2 pi i/(Ns R))
+//     X     = DFT_R(x)
+//     out[(j div Ns) Ns R + k + r Ns] = X_r
+// and the last pass leaves natural order.  A lane owns butterflies
+// j = lane + b L (b < P/R); between passes the values go through the line's
+// LDS buffer.  DFT_R runs in registers, composite R by one Cooley-Tukey step
+// with compile-time twiddles.
+#pragma once
+
+#include "cx.hpp"
+#include "shapes.hpp"
+
+namespace lsr {
+
+// a * exp(DIR 2 pi i M / R), constants folded at compile time.
+template <int R, int M, int DIR, typename T>
+__device__ __forceinline__ cx<T> twc(cx<T> a) {
+    constexpr int m = ((M % R) + R) % R;
+    if constexpr (m == 0) {
+        return a;
+    } else if constexpr (4 * m == R) {
+        return rot_q<DIR>(a);
+    } else if constexpr (2 * m == R) {
+        return {-a.re, -a.im};
+    } else if constexpr (4 * m == 3 * R) {
+        return rot_q<-DIR>(a);
+    } else if constexpr (8 * m == R || 8 * m == 3 * R || 8 * m == 5 * R || 8 * m == 7 * R) {
+        // (+-1 +- i)/sqrt(2): two adds and two multiplies
+        constexpr double th = 2.0 * kPi * m / R;
+        constexpr T c = (T)ce_cos(th);
+        constexpr T s = (T)(DIR * ce_sin(th));
+        constexpr T h = (T)0.70710678118654752440084436210484904;
+        constexpr T cs = c > 0 ? h : -h;
+        constexpr T ss = s > 0 ? h : -h;
+        if constexpr ((cs > 0) == (ss > 0)) {
+            // c == s
+            return {(a.re - a.im) * cs, (a.re + a.im) * cs};
+        } else {
+            // c == -s
+            return {(a.re + a.im) * cs, (a.im - a.re) * cs};
+        }
+    } else {
+        constexpr double th = 2.0 * kPi * m / R;
+        constexpr T c = (T)ce_cos(th);
+        constexpr T s = (T)(DIR * ce_sin(th));
+        return {a.re * c - a.im * s, a.re * s + a.im * c};
+    }
+}
+
+// In-place DFT of length R in registers: X_k = sum_n x_n exp(DIR 2 pi i nk/R).
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft(cx<T>* x) {
+    if constexpr (R == 1) {
+        return;
+    } else if constexpr (R == 2) {
+        cx<T> a = x[0], b = x[1];
+        x[0] = a + b;
+        x[1] = a - b;
+    } else if constexpr (R == 3) {
+        constexpr T s3 = (T)0.86602540378443864676372317075293618;
+        cx<T> t = x[1] + x[2];
+        cx<T> d = scale(rot_q<DIR>(x[1] - x[2]), s3);
+        cx<T> m = {x[0].re - (T)0.5 * t.re, x[0].im - (T)0.5 * t.im};
+        x[0] = x[0] + t;
+        x[1] = m + d;
+        x[2] = m - d;
+    } else if constexpr (R == 4) {
+        cx<T> t0 = x[0] + x[2], t1 = x[0] - x[2];
+        cx<T> t2 = x[1] + x[3], t3 = rot_q<DIR>(x[1] - x[3]);
+        x[0] = t0 + t2;
+        x[2] = t0 - t2;
+        x[1] = t1 + t3;
+        x[3] = t1 - t3;
+    } else {
+        // R = A * B: A decimated sub-DFTs of length B, twiddles exp(DIR 2 pi i n1 k2/R),
+        // then B DFTs of length A; X[k2 + B k1].
+        constexpr int A = (R % 4 == 0) ? 4 : ((R % 3 == 0) ? 3 : 2);
+        constexpr int B = R / A;
+        cx<T> y[R];
+        sfor<0, A>([&](auto n1c) {
+            constexpr int n1 = decltype(n1c)::value;
+            cx<T> s[B];
+            sfor<0, B>([&](auto mc) { s[decltype(mc)::value] = x[n1 + A * decltype(mc)::value]; });
+            dft<B, DIR>(s);
+            sfor<0, B>([&](auto kc) {
+                constexpr int k2 = decltype(kc)::value;
+                y[n1 * B + k2] = twc<R, n1 * k2, DIR>(s[k2]);
+            });
+        });
+        sfor<0, B>([&](auto kc) {
+            constexpr int k2 = decltype(kc)::value;
+            cx<T> s[A];
+            sfor<0, A>([&](auto n1c) { s[decltype(n1c)::value] = y[decltype(n1c)::value * B + k2]; });
+            dft<A, DIR>(s);
+            sfor<0, A>([&](auto k1c) { x[k2 + B * decltype(k1c)::value] = s[decltype(k1c)::value]; });
+        });
+    }
+}
+
+// Synchronisation among the lanes of one line: a line inside one wavefront
+// needs only a wave-level fence; a line spanning several waves a barrier.
+template <class S>
+__device__ __forceinline__ void line_sync() {
+    if constexpr (S::L <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// Load R consecutive twiddles (16-byte vector loads; R even or R == 3).
+template <int R, typename T>
+__device__ __forceinline__ void load_tw(cx<T>* w, const cx<T>* __restrict__ src) {
+    if constexpr (sizeof(cx<T>) == 8 && (R % 2 == 0)) {
+        const float4* s4 = reinterpret_cast<const float4*>(src);
+        sfor<0, R / 2>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            float4 q = s4[i];
+            w[2 * i] = {(T)q.x, (T)q.y};
+            w[2 * i + 1] = {(T)q.z, (T)q.w};
+        });
+    } else {
+        sfor<0, R>([&](auto ic) { w[decltype(ic)::value] = src[decltype(ic)::value]; });
+    }
+}
+
+// Butterflies of pass PASS in direction DIR on the lane's registers.
+template <class S, int DIR, int PASS, typename T>
+__device__ __forceinline__ void pass_compute(cx<T>* v, int lane, const cx<T>* __restrict__ tw) {
+    constexpr int R = S::rad(DIR, PASS);
+    constexpr int Ns = S::ns(DIR, PASS);
+    constexpr int B = S::P / R;
+    sfor<0, B>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        cx<T>* x = v + b * R;
+        if constexpr (Ns > 1) {
+            const int j = lane + b * S::L;
+            const int k = j % Ns;
+            cx<T> w[R];
+            load_tw<R>(w, tw + S::tw_off(DIR, PASS) + k * R);
+            sfor<1, R>([&](auto rc) {
+                constexpr int r = decltype(rc)::value;
+                x[r] = cmul(x[r], w[r]);
+            });
+        }
+        dft<R, DIR>(x);
+    });
+}
+
+// Write the outputs of pass PASS to their Stockham positions in the line.
+template <class S, int DIR, int PASS, typename T>
+__device__ __forceinline__ void pass_scatter(const cx<T>* v, cx<T>* line, int lane) {
+    constexpr int R = S::rad(DIR, PASS);
+    constexpr int Ns = S::ns(DIR, PASS);
+    constexpr int B = S::P / R;
+    sfor<0, B>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        const int j = lane + b * S::L;
+        const int k = j % Ns;
+        const int base = (j / Ns) * Ns * R + k;
+        sfor<0, R>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            line[S::pad(base + r * Ns)] = v[b * R + r];
+        });
+    });
+}
+
+// Read the inputs of a pass with radix R: v[b R + r] = line[j + r N/R].
+template <class S, int R, typename T>
+__device__ __forceinline__ void gather_in(cx<T>* v, const cx<T>* line, int lane) {
+    constexpr int B = S::P / R;
+    sfor<0, B>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        const int j = lane + b * S::L;
+        sfor<0, R>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            v[b * R + r] = line[S::pad(j + r * (S::N / R))];
+        });
+    });
+}
+
+// Inverse of gather_in: line[j + r N/R] = v[b R + r] (natural order out).
+template <class S, int R, typename T>
+__device__ __forceinline__ void scatter_out(const cx<T>* v, cx<T>* line, int lane) {
+    constexpr int B = S::P / R;
+    sfor<0, B>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        const int j = lane + b * S::L;
+        sfor<0, R>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            line[S::pad(j + r * (S::N / R))] = v[b * R + r];
+        });
+    });
+}
+
+// Grid index of register v[b R + r] in the layout gather_in/scatter_out use.
+template <class S, int R>
+__device__ __forceinline__ int reg_pos(int lane, int b, int r) {
+    return lane + b * S::L + r * (S::N / R);
+}
+
+// Radix of the first forward pass (= last inverse pass) and of the last
+// forward pass (= first inverse pass).
+template <class S> constexpr int R_FIRST = S::rad_fwd(0);
+template <class S> constexpr int R_LAST = S::rad_fwd(S::NP - 1);
+
+// Full 1D transform of one line.  On entry v holds the pass-0 inputs
+// (gather_in order for the first radix of DIR); on exit the natural-order
+// outputs in the gather_in order of the last radix of DIR.  The line buffer
+// is scratch; the caller synchronises before reusing it.
+template <class S, int DIR, typename T>
+__device__ __forceinline__ void fft_line(cx<T>* v, cx<T>* line, int lane, const cx<T>* __restrict__ tw) {
+    sfor<0, S::NP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        pass_compute<S, DIR, p>(v, lane, tw);
+        if constexpr (p + 1 < S::NP) {
+            pass_scatter<S, DIR, p>(v, line, lane);
+            line_sync<S>();
+            gather_in<S, S::rad(DIR, p + 1)>(v, line, lane);
+            line_sync<S>();
+        }
+    });
+}
+
+}  // namespace lsr

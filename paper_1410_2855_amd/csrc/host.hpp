@@ -1,0 +1,73 @@
+// host.hpp -- host-side plan object, error reporting and table builders.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lsr.h"
+#include "desc.hpp"
+#include "launch.hpp"
+
+namespace lsr {
+
+int set_err(int code, const char* fmt, ...);
+
+#define LSR_HIP(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::lsr::set_err(LSR_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Keeps the caller's current device and restores it on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// FP64 (or FP32-emulating) table builders; pure host arithmetic.
+std::vector<double> build_twiddles(const ShapeInfo& s, bool fp32_arith);   // interleaved re, im
+std::vector<double> build_hx(int N, double dx, double lambda, double L);   // interleaved, 1/N folded
+std::vector<double> build_pump_cos(int N, double dx, double period);
+std::vector<double> build_focal(int N, double dx, double lambda, double F); // interleaved
+
+struct lsr_plan_impl;
+
+}  // namespace lsr
+
+struct lsr_plan_s {
+    int device = 0;
+    int N = 0;
+    int prec = 0;
+    double dx = 0, lambda = 0, L = 0, F = 0, R = 1;
+    lsr_aperture ap{};
+    double N0 = 0, T1 = 1, mod_amp = 0, mod_period = 0;
+    hipStream_t stream = nullptr;
+    const lsr::Launchers* kern = nullptr;
+    lsr::ShapeInfo shape{};
+    lsr::CavDesc d{};          // template descriptor; E/Ninv filled per call
+    // owned device memory
+    void* d_tw = nullptr;
+    void* d_hx = nullptr;
+    void* d_pump = nullptr;
+    void* d_foc = nullptr;
+    double* d_partials = nullptr;
+    double* d_trace = nullptr;
+    unsigned* d_counters = nullptr;
+    void* d_scratch = nullptr;       // lazily, for lsr_diag
+    double* d_radial_part = nullptr; // lazily
+    double* d_diag_out = nullptr;    // lazily
+    int trace_cap = 0;
+    unsigned long long trips_done = 0;   // host shadow of counters[CNT_TRIPS]
+    int last_n = 0;
+    size_t real_bytes() const { return prec == lsr::PREC_FP64 ? 8 : 4; }
+};

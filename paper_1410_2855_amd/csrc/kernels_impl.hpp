@@ -1,0 +1,58 @@
+// kernels_impl.hpp -- one-cavity kernels (row pass, column pass, diagnostics)
+// and their launchers, instantiated per grid size by the k*.hip units.
+#pragma once
+
+#include "launch.hpp"
+#include "map.hpp"
+
+namespace lsr {
+
+template <class S, typename T, int MODE>
+__global__ __launch_bounds__(S::THREADS) void k_row(CavDesc d) {
+    __shared__ cx<T> lds[S::LDS_ELEMS];
+    __shared__ double red[4 * 16];
+    row_task<S, T, MODE>(d, blockIdx.x, lds, red);
+}
+
+template <class S, typename T, int MODE>
+__global__ __launch_bounds__(S::THREADS) void k_col(CavDesc d) {
+    __shared__ cx<T> lds[S::LDS_ELEMS];
+    if constexpr (MODE == COL_PROP) {
+        // the row pass of this trip is complete (stream order): fold its
+        // per-block sums into the trace ring
+        if (blockIdx.x == 0 && threadIdx.x < 64) finalize_sums(d);
+    }
+    col_task<S, T, MODE>(d, blockIdx.x, lds);
+}
+
+template <class S, typename T>
+int launch_row_t(const CavDesc& d, int mode, hipStream_t st) {
+    const dim3 g(S::N / S::LPW), b(S::THREADS);
+    switch (mode) {
+    case ROW_FIRST: hipLaunchKernelGGL((k_row<S, T, ROW_FIRST>), g, b, 0, st, d); break;
+    case ROW_MID:   hipLaunchKernelGGL((k_row<S, T, ROW_MID>), g, b, 0, st, d); break;
+    case ROW_LAST:  hipLaunchKernelGGL((k_row<S, T, ROW_LAST>), g, b, 0, st, d); break;
+    case ROW_DIAG:  hipLaunchKernelGGL((k_row<S, T, ROW_DIAG>), g, b, 0, st, d); break;
+    default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <class S, typename T>
+int launch_col_t(const CavDesc& d, int mode, hipStream_t st) {
+    const dim3 g(S::N / S::LPW), b(S::THREADS);
+    switch (mode) {
+    case COL_PROP: hipLaunchKernelGGL((k_col<S, T, COL_PROP>), g, b, 0, st, d); break;
+    case COL_DIAG: hipLaunchKernelGGL((k_col<S, T, COL_DIAG>), g, b, 0, st, d); break;
+    default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <class S, typename T>
+const Launchers* make_launchers() {
+    static const Launchers L{&launch_row_t<S, T>, &launch_col_t<S, T>, shape_info<S>()};
+    return &L;
+}
+
+}  // namespace lsr

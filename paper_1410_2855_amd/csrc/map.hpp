@@ -1,0 +1,405 @@
+// map.hpp -- the round trip as workgroup tasks: row blocks and column blocks.
+//
+// One round trip of the cavity map (paper, Intro Eq. (1); Sec. 2.2 Eqs.
+// (11)-(12); diffraction as the operator exponent of Sec. 2.3 Eq. (25)):
+//     G       = sqrt(R) A exp(N_n/2) E_n              local step
+//     N_{n+1} = N_n + (N0 - N_n)/T1 - N_n |E_n|^2      inversion update
+//     E_{n+1} = IFFT2( H FFT2(G) )                    diffraction
+// is carried by two streaming passes over the field:
+//   row task (LPW rows):  [inverse row DFT of trip n-1] -> E_n -> local step,
+//                         inversion update, diagnostics sums -> forward row DFT
+//   column task (LPW columns): forward column DFT -> x H -> inverse column DFT
+// so trip n's inverse row DFT is fused with trip n+1's local step and
+// forward row DFT.  Each pass reads and writes the field once: 24 B/point for
+// the row pass (field and inversion), 16 B/point for the column pass.
+//
+// Internal field layout between passes ("tiled"): the N x N array is cut into
+// LPW x LPW tiles stored contiguously, tiles ordered row-block-major, and
+// elements row-major inside a tile.  Row block rb (rows rb*LPW..) is then one
+// contiguous span, exactly the span rows rb*LPW.. occupy in row-major order,
+// so the first and last row passes convert in place; column block cb is N/LPW
+// contiguous tiles.  Every global access is a whole tile (>= 128 B for the
+// FP32 shapes), independent of N.
+#pragma once
+
+#include "desc.hpp"
+#include "fft.hpp"
+
+namespace lsr {
+
+template <typename T> struct V16;
+template <> struct V16<float> { using type = float4; };
+template <> struct V16<double> { using type = double2; };
+
+template <typename T> constexpr int EPC = 16 / (int)sizeof(cx<T>);  // elements per 16-byte chunk
+
+template <typename T>
+__device__ __forceinline__ void unpack16(const typename V16<T>::type& q, cx<T>* e) {
+    if constexpr (sizeof(T) == 4) {
+        e[0] = {q.x, q.y};
+        e[1] = {q.z, q.w};
+    } else {
+        e[0] = {q.x, q.y};
+    }
+}
+template <typename T>
+__device__ __forceinline__ typename V16<T>::type pack16(const cx<T>* e) {
+    if constexpr (sizeof(T) == 4) return float4{e[0].re, e[0].im, e[1].re, e[1].im};
+    else return double2{e[0].re, e[0].im};
+}
+
+__device__ __forceinline__ float ex(float x) { return expf(x); }
+__device__ __forceinline__ double ex(double x) { return exp(x); }
+__device__ __forceinline__ void sc(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sc(double x, double* s, double* c) { sincos(x, s, c); }
+
+__device__ __forceinline__ int signed_idx(int q, int n) { return (2 * q < n) ? q : q - n; }
+
+// round(sqrt(s)) for an integer s >= 0, exactly: k with k^2 - k < s <= k^2 + k.
+__device__ __forceinline__ int round_sqrt(int s) {
+    int k = (int)(sqrtf((float)s) + 0.5f);
+    while ((long long)k * k + k < s) ++k;
+    while (k > 0 && (long long)k * k - k >= s) --k;
+    return k;
+}
+
+// ---------------------------------------------------------------------------
+// Staging between HBM and the LDS line buffers (16-byte chunks).
+// Row spans: LAYOUT 0 = row-major rows, 1 = tiled row block.
+template <class S, typename T, int LAYOUT>
+__device__ __forceinline__ void row_chunk_pos(int c, int& l, int& x) {
+    const int o = c * EPC<T>;
+    if constexpr (LAYOUT == 0) {
+        l = o / S::N;
+        x = o % S::N;
+    } else {
+        constexpr int TT = S::LPW * S::LPW;
+        const int t = o / TT, rem = o % TT;
+        l = rem / S::LPW;
+        x = t * S::LPW + rem % S::LPW;
+    }
+}
+
+template <class S, typename T, int LAYOUT>
+__device__ __forceinline__ void stage_in_rows(const cx<T>* __restrict__ blk, cx<T>* lds) {
+    using V = typename V16<T>::type;
+    constexpr int NCH = S::LPW * S::N / EPC<T>;
+    static_assert(NCH % S::THREADS == 0, "row staging must tile the workgroup");
+    constexpr int IT = NCH / S::THREADS;
+    const V* src = reinterpret_cast<const V*>(blk);
+    V q[IT];
+    sfor<0, IT>([&](auto ic) { q[decltype(ic)::value] = src[threadIdx.x + decltype(ic)::value * S::THREADS]; });
+    sfor<0, IT>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        int l, x;
+        row_chunk_pos<S, T, LAYOUT>(threadIdx.x + i * S::THREADS, l, x);
+        cx<T> e[EPC<T>];
+        unpack16<T>(q[i], e);
+        sfor<0, EPC<T>>([&](auto kc) { lds[l * S::LINE + S::pad(x + decltype(kc)::value)] = e[decltype(kc)::value]; });
+    });
+}
+
+template <class S, typename T, int LAYOUT>
+__device__ __forceinline__ void stage_out_rows(cx<T>* __restrict__ blk, const cx<T>* lds) {
+    using V = typename V16<T>::type;
+    constexpr int NCH = S::LPW * S::N / EPC<T>;
+    constexpr int IT = NCH / S::THREADS;
+    V* dst = reinterpret_cast<V*>(blk);
+    sfor<0, IT>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const int c = threadIdx.x + i * S::THREADS;
+        int l, x;
+        row_chunk_pos<S, T, LAYOUT>(c, l, x);
+        cx<T> e[EPC<T>];
+        sfor<0, EPC<T>>([&](auto kc) { e[decltype(kc)::value] = lds[l * S::LINE + S::pad(x + decltype(kc)::value)]; });
+        dst[c] = pack16<T>(e);
+    });
+}
+
+// Column block cb of the tiled layout: tiles (i, cb), i = 0..N/LPW-1.
+template <class S, typename T>
+__device__ __forceinline__ size_t col_chunk(int c, int cb, int& line, int& y) {
+    constexpr int TT = S::LPW * S::LPW;
+    constexpr int CPT = TT / EPC<T>;
+    const int i = c / CPT;
+    const int o = (c % CPT) * EPC<T>;
+    line = o % S::LPW;
+    y = i * S::LPW + o / S::LPW;
+    return ((size_t)i * S::LPW * S::N + (size_t)cb * TT + o) / EPC<T>;
+}
+
+template <class S, typename T>
+__device__ __forceinline__ void stage_in_cols(const cx<T>* __restrict__ E, int cb, cx<T>* lds) {
+    using V = typename V16<T>::type;
+    static_assert(S::LPW % EPC<T> == 0, "a chunk must stay inside one tile row");
+    constexpr int NCH = S::N * S::LPW / EPC<T>;
+    static_assert(NCH % S::THREADS == 0, "column staging must tile the workgroup");
+    constexpr int IT = NCH / S::THREADS;
+    const V* src = reinterpret_cast<const V*>(E);
+    V q[IT];
+    size_t off[IT];
+    int ln[IT], yy[IT];
+    sfor<0, IT>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        off[i] = col_chunk<S, T>(threadIdx.x + i * S::THREADS, cb, ln[i], yy[i]);
+    });
+    sfor<0, IT>([&](auto ic) { q[decltype(ic)::value] = src[off[decltype(ic)::value]]; });
+    sfor<0, IT>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        cx<T> e[EPC<T>];
+        unpack16<T>(q[i], e);
+        sfor<0, EPC<T>>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            lds[(ln[i] + k) * S::LINE + S::pad(yy[i])] = e[k];
+        });
+    });
+}
+
+template <class S, typename T>
+__device__ __forceinline__ void stage_out_cols(cx<T>* __restrict__ E, int cb, const cx<T>* lds) {
+    using V = typename V16<T>::type;
+    constexpr int NCH = S::N * S::LPW / EPC<T>;
+    constexpr int IT = NCH / S::THREADS;
+    V* dst = reinterpret_cast<V*>(E);
+    sfor<0, IT>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        int line, y;
+        const size_t off = col_chunk<S, T>(threadIdx.x + i * S::THREADS, cb, line, y);
+        cx<T> e[EPC<T>];
+        sfor<0, EPC<T>>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            e[k] = lds[(line + k) * S::LINE + S::pad(y)];
+        });
+        dst[off] = pack16<T>(e);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Reductions (wave64 butterflies, then LDS across waves, fixed order).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+template <class S>
+__device__ __forceinline__ void block_sums_store(double* acc, double* red, double* out) {
+    constexpr int NW = S::THREADS / 64;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = wave_sum(acc[q]);
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[(tid >> 6) * 4 + q] = acc[q];
+    }
+    __syncthreads();
+    if (tid < 4) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += red[w * 4 + tid];
+        out[tid] = s;
+    }
+}
+
+// Ordered reduction of a cavity's row-block partials into its trace ring;
+// run by one full wavefront.  Flags the first non-finite trip.
+__device__ __forceinline__ void finalize_sums(const CavDesc& d) {
+    const int lane = threadIdx.x & 63;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int rb = lane; rb < d.nrb; rb += 64) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s[q] += d.partials[4 * rb + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] = wave_sum(s[q]);
+    if (lane == 0) {
+        const unsigned t = d.counters[CNT_TRIPS];
+        const unsigned slot = t % (unsigned)d.trace_cap;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d.trace[4 * (size_t)slot + q] = s[q];
+        const bool bad = !isfinite(s[0]) || !isfinite(s[1]) || !isfinite(s[2]) || !isfinite(s[3]);
+        if (bad && d.counters[CNT_NONFINITE] == 0u) d.counters[CNT_NONFINITE] = t + 1u;
+        d.counters[CNT_TRIPS] = t + 1u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Local step, inversion update and diagnostics sums on the lane's points of
+// row y (register order of the first forward radix = natural x order).
+template <class S, typename T, int MODE>
+__device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc& d, int y, int lane,
+                                           double* acc) {
+    constexpr int R = R_FIRST<S>;
+    constexpr int B = S::P / R;
+    const T dx = (T)d.dx;
+    const T half = (T)(0.5 * S::N);
+    const T Y = ((T)y - half) * dx;
+    const T Y2 = Y * Y;
+    const T sqR = (T)d.sqrtR, N0 = (T)d.N0, iT1 = (T)d.inv_T1, mamp = (T)d.mod_amp;
+    const T ir = (T)d.inv_r0sq;
+    const int kind = d.ap_kind, hord = d.ap_half_order;
+    const T* pc = static_cast<const T*>(d.pump_c);
+    const cx<T>* foc = static_cast<const cx<T>*>(d.foc);
+    const T* mask = static_cast<const T*>(d.mask);
+    T* ninv = static_cast<T*>(d.Ninv);
+    const T pcy = pc ? pc[y] : (T)0;
+    const cx<T> fy = foc ? foc[y] : cx<T>{(T)1, (T)0};
+    sfor<0, B>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        sfor<0, R>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            const int x = reg_pos<S, R>(lane, b, r);
+            const cx<T> e = v[b * R + r];
+            const T n = nv[b * R + r];
+            const T I = norm2(e);
+            T A = (T)1;
+            if (kind == AP_MASK) {
+                A = mask[(size_t)y * S::N + x];
+            } else if (kind != AP_NONE) {
+                const T X = ((T)x - half) * dx;
+                const T u = (X * X + Y2) * ir;
+                T p = u;
+                if (kind == AP_SUPERGAUSS)
+                    for (int k = 1; k < hord; ++k) p *= u;
+                A = ex(-p);
+            }
+            const T eh = ex((T)0.5 * n);          // frozen-inversion amplitude gain
+            const T A2 = A * A;
+            const T aeh = A * eh;
+            acc[0] += (double)I;
+            acc[1] += (double)(A2 * I);
+            acc[2] += (double)(aeh * aeh * I);
+            acc[3] += (double)n;
+            cx<T> g = scale(e, sqR * aeh);
+            if (foc) g = cmul(g, cmul(foc[x], fy));
+            v[b * R + r] = g;
+            if constexpr (MODE != ROW_DIAG) {
+                const T pump = pc ? N0 * ((T)1 + mamp * pc[x] * pcy) : N0;
+                ninv[(size_t)y * S::N + x] = n + (pump - n) * iT1 - n * I;
+            }
+        });
+    });
+}
+
+// ---------------------------------------------------------------------------
+template <class S, typename T, int MODE>
+__device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, double* red) {
+    const int tid = threadIdx.x;
+    const int line = tid / S::L, lane = tid % S::L;
+    const int y = rb * S::LPW + line;
+    cx<T>* blk = static_cast<cx<T>*>(d.E) + (size_t)rb * S::LPW * S::N;
+    const cx<T>* tw = static_cast<const cx<T>*>(d.tw);
+    cx<T>* myl = lds + line * S::LINE;
+    constexpr int RF = R_FIRST<S>;
+    constexpr int RL = R_LAST<S>;
+
+    T nv[S::P];
+    if constexpr (MODE != ROW_LAST) {
+        const T* ninv = static_cast<const T*>(d.Ninv) + (size_t)y * S::N;
+        sfor<0, S::P / RF>([&](auto bc) {
+            sfor<0, RF>([&](auto rc) {
+                constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
+                nv[b * RF + r] = ninv[reg_pos<S, RF>(lane, b, r)];
+            });
+        });
+    }
+    if constexpr (MODE == ROW_FIRST || MODE == ROW_DIAG) stage_in_rows<S, T, 0>(blk, lds);
+    else stage_in_rows<S, T, 1>(blk, lds);
+    __syncthreads();
+
+    cx<T> v[S::P];
+    if constexpr (MODE == ROW_MID || MODE == ROW_LAST) {
+        gather_in<S, RL>(v, myl, lane);
+        line_sync<S>();
+        fft_line<S, INV>(v, myl, lane, tw);
+    } else {
+        gather_in<S, RF>(v, myl, lane);
+        line_sync<S>();
+    }
+    if constexpr (MODE == ROW_LAST) {
+        scatter_out<S, RF>(v, myl, lane);
+        __syncthreads();
+        stage_out_rows<S, T, 0>(blk, lds);
+        return;
+    } else {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        local_step<S, T, MODE>(v, nv, d, y, lane, acc);
+        block_sums_store<S>(acc, red, d.partials + 4 * rb);
+        fft_line<S, FWD>(v, myl, lane, tw);
+        scatter_out<S, RL>(v, myl, lane);
+        __syncthreads();
+        cx<T>* dst = blk;
+        if constexpr (MODE == ROW_DIAG) dst = static_cast<cx<T>*>(d.scratch) + (size_t)rb * S::LPW * S::N;
+        stage_out_rows<S, T, 1>(dst, lds);
+    }
+}
+
+template <class S, typename T, int MODE>
+__device__ __forceinline__ void col_task(const CavDesc& d, int cb, cx<T>* lds) {
+    const int tid = threadIdx.x;
+    const int line = tid / S::L, lane = tid % S::L;
+    cx<T>* E = static_cast<cx<T>*>(MODE == COL_DIAG ? d.scratch : d.E);
+    const cx<T>* tw = static_cast<const cx<T>*>(d.tw);
+    cx<T>* myl = lds + line * S::LINE;
+    constexpr int RF = R_FIRST<S>;
+    constexpr int RL = R_LAST<S>;
+    constexpr int B = S::P / RL;
+
+    stage_in_cols<S, T>(E, cb, lds);
+    __syncthreads();
+    cx<T> v[S::P];
+    gather_in<S, RF>(v, myl, lane);
+    line_sync<S>();
+    fft_line<S, FWD>(v, myl, lane, tw);
+    const int kx = cb * S::LPW + line;
+    const int px = signed_idx(kx, S::N);
+
+    if constexpr (MODE == COL_DIAG) {
+        // far-field radial spectrum |FFT2(G)|^2 binned by round(|(p~, q~)|)
+        __syncthreads();
+        double* hist = reinterpret_cast<double*>(lds);
+        for (int i = tid; i < d.nbins; i += S::THREADS) hist[i] = 0.0;
+        __syncthreads();
+        sfor<0, B>([&](auto bc) {
+            sfor<0, RL>([&](auto rc) {
+                constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
+                const int q = signed_idx(reg_pos<S, RL>(lane, b, r), S::N);
+                atomicAdd(&hist[round_sqrt(px * px + q * q)], (double)norm2(v[b * RL + r]));
+            });
+        });
+        __syncthreads();
+        for (int i = tid; i < d.nbins; i += S::THREADS) d.radial_part[(size_t)cb * d.nbins + i] = hist[i];
+        return;
+    } else {
+        // propagator H(kx, ky) = exp(-i pi lambda L (fx^2 + fy^2)) / N^2
+        if (d.prec == PREC_PLAIN) {
+            const T c = (T)d.phase_c, inn = (T)d.inv_nn;
+            const int px2 = px * px;
+            sfor<0, B>([&](auto bc) {
+                sfor<0, RL>([&](auto rc) {
+                    constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
+                    const int q = signed_idx(reg_pos<S, RL>(lane, b, r), S::N);
+                    T s, co;
+                    sc((T)(px2 + q * q) * c, &s, &co);
+                    v[b * RL + r] = cmul(v[b * RL + r], cx<T>{co * inn, -s * inn});
+                });
+            });
+        } else {
+            const cx<T>* hx = static_cast<const cx<T>*>(d.hx);
+            const cx<T> hk = hx[kx];
+            sfor<0, B>([&](auto bc) {
+                sfor<0, RL>([&](auto rc) {
+                    constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
+                    const cx<T> h = cmul(hk, hx[reg_pos<S, RL>(lane, b, r)]);
+                    v[b * RL + r] = cmul(v[b * RL + r], h);
+                });
+            });
+        }
+        fft_line<S, INV>(v, myl, lane, tw);
+        scatter_out<S, RF>(v, myl, lane);
+        __syncthreads();
+        stage_out_cols<S, T>(E, cb, lds);
+    }
+}
+
+}  // namespace lsr

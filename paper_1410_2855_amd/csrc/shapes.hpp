@@ -1,0 +1,121 @@
+// shapes.hpp -- compile-time description of the per-line FFT of each grid
+// size: lanes per line, lines per workgroup, and the Stockham radix sequence.
+// Shared by host (table builders, packer) and device (kernels).
+//
+// A "line" is one row (row pass) or one column (column pass) of the N x N
+// grid.  A line is transformed by L lanes, each holding P = N/L points in
+// registers; a workgroup handles LPW lines.  The same LPW is the edge of the
+// square tile of the internal field layout (see layout notes in kernels.hip):
+// row-pass workgroups own LPW consecutive rows, column-pass workgroups LPW
+// consecutive columns, and every global access is a whole LPW x LPW tile.
+//
+// Forward passes use RAD[0..NP-1] in order; inverse passes the reverse order,
+// so the inverse's last radix equals the forward's first (and vice versa) and
+// the register layout at the end of one transform is the start layout of the
+// next: the row pass goes inverse -> local step -> forward and the column
+// pass forward -> propagator -> inverse with no LDS exchange at the seam.
+#pragma once
+
+#include <cstdint>
+
+namespace lsr {
+
+enum : int { FWD = -1, INV = +1 };   // sign of the DFT exponent
+
+template <int N_, int L_, int LPW_, int... R>
+struct Shape {
+    static constexpr int N = N_;
+    static constexpr int L = L_;
+    static constexpr int LPW = LPW_;
+    static constexpr int P = N_ / L_;
+    static constexpr int THREADS = L_ * LPW_;
+    static constexpr int NP = sizeof...(R);
+
+    static constexpr int rad_fwd(int s) {
+        constexpr int a[] = {R...};
+        return a[s];
+    }
+    // radix of pass s in direction dir
+    static constexpr int rad(int dir, int s) {
+        return dir == FWD ? rad_fwd(s) : rad_fwd(NP - 1 - s);
+    }
+    // product of the radices of the passes before s (Stockham sub-length)
+    static constexpr int ns(int dir, int s) {
+        int p = 1;
+        for (int i = 0; i < s; ++i) p *= rad(dir, i);
+        return p;
+    }
+    static constexpr int prod() {
+        int p = 1;
+        for (int i = 0; i < NP; ++i) p *= rad_fwd(i);
+        return p;
+    }
+    // twiddle-table segment of pass s: Ns*R entries (k*R + r) when Ns > 1
+    static constexpr int tw_len(int dir, int s) { return ns(dir, s) > 1 ? ns(dir, s) * rad(dir, s) : 0; }
+    static constexpr int tw_off(int dir, int s) {
+        int o = 0;
+        if (dir == INV)
+            for (int i = 0; i < NP; ++i) o += tw_len(FWD, i);
+        for (int i = 0; i < s; ++i) o += tw_len(dir, i);
+        return o;
+    }
+    static constexpr int TW_TOTAL = tw_off(INV, NP);
+
+    // LDS: one padded line per handled line; one spare element per 16 keeps
+    // the Stockham scatter of small sub-lengths free of bank conflicts.
+    static constexpr int pad(int i) { return i + (i >> 4); }
+    static constexpr int LINE = N_ + (N_ >> 4) + 2;
+    static constexpr int LDS_ELEMS = LPW_ * LINE;
+
+    static constexpr bool valid() {
+        if (prod() != N_ || N_ % L_ != 0 || N_ % LPW_ != 0) return false;
+        for (int i = 0; i < NP; ++i)
+            if (P % rad_fwd(i) != 0) return false;
+        if (THREADS > 1024 || THREADS % 64 != 0) return false;
+        if (L_ > 64 && L_ % 64 != 0) return false;
+        if (64 % L_ != 0 && L_ < 64) return false;
+        return true;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// The compiled shapes.  FP32 complex field (8 B/point):
+using S256  = Shape<256, 16, 16, 16, 16>;
+using S384  = Shape<384, 16, 16, 8, 12, 4>;
+using S512  = Shape<512, 32, 8, 8, 8, 8>;
+using S768  = Shape<768, 32, 8, 8, 12, 8>;
+using S1024 = Shape<1024, 64, 4, 4, 16, 16>;
+using S2048 = Shape<2048, 64, 4, 8, 16, 16>;
+using S4096 = Shape<4096, 256, 4, 16, 16, 16>;
+// FP64 complex field (16 B/point): half the lines per workgroup.
+using D256  = Shape<256, 16, 8, 16, 16>;
+using D384  = Shape<384, 16, 8, 8, 12, 4>;
+using D512  = Shape<512, 32, 4, 8, 8, 8>;
+using D768  = Shape<768, 32, 4, 8, 12, 8>;
+using D1024 = Shape<1024, 64, 2, 4, 16, 16>;
+using D2048 = Shape<2048, 64, 2, 8, 16, 16>;
+
+static_assert(S256::valid() && S384::valid() && S512::valid() && S768::valid() &&
+              S1024::valid() && S2048::valid() && S4096::valid(), "bad fp32 shape");
+static_assert(D256::valid() && D384::valid() && D512::valid() && D768::valid() &&
+              D1024::valid() && D2048::valid(), "bad fp64 shape");
+
+// Runtime description of a shape (host side).
+struct ShapeInfo {
+    int N, L, LPW, NP;
+    int rad[8];
+    int tw_total;
+    int threads;
+};
+
+template <class S>
+inline ShapeInfo shape_info() {
+    ShapeInfo s{};
+    s.N = S::N; s.L = S::L; s.LPW = S::LPW; s.NP = S::NP;
+    for (int i = 0; i < S::NP; ++i) s.rad[i] = S::rad_fwd(i);
+    s.tw_total = S::TW_TOTAL;
+    s.threads = S::THREADS;
+    return s;
+}
+
+}  // namespace lsr
