@@ -58,9 +58,9 @@ typedef enum {
 } lsr_status;
 
 /* Arithmetic form of a plan.
- * PLAIN:     complex FP32 field and FFTs; twiddles and the propagator phase
- *            pi lambda L (fx^2+fy^2) generated in FP32 arithmetic; the
- *            per-lane diagnostics sums in FP32.
+ * PLAIN:     complex FP32 field and FFTs; twiddles generated in FP32
+ *            arithmetic and the propagator phase pi lambda L (fx^2+fy^2)
+ *            evaluated in FP32 on the device; diagnostics sums in FP64.
  * FP64TAB:   complex FP32 field and FFTs; twiddles and the propagator phase
  *            generated in FP64 and reduced modulo one turn before rounding
  *            to FP32; the propagator is the separable product hx(p) hx(q);
@@ -138,8 +138,8 @@ int lsr_plan_set_stream(lsr_plan p, void* hip_stream);
  * plus 1.  The per-trip diagnostics sums go to the plan's trace ring. */
 int lsr_roundtrips(lsr_plan p, void* E, void* Ninv, int n_trips);
 
-/* Wait for the plan's stream; LSR_ENONFINITE if any trip of the calls since
- * the last lsr_sync/lsr_trace saw a non-finite state. */
+/* Wait for the plan's stream; LSR_ENONFINITE if any trip since the last
+ * lsr_sync saw a non-finite state (the flag is cleared by the report). */
 int lsr_sync(lsr_plan p);
 
 /* Copy the raw per-trip sums of the last lsr_roundtrips call (oldest first)
@@ -148,6 +148,12 @@ int lsr_sync(lsr_plan p);
  * Copies min(capacity, n_trips of that call, ring size) records; returns the
  * count (>= 0) or a negative status.  Synchronises the stream. */
 int lsr_trace(lsr_plan p, double* out, int capacity);
+
+/* Profiling form of lsr_roundtrips: the same launches, each bracketed by
+ * HIP events on the plan's stream.  Writes the mean duration in ms of the
+ * row-pass kernel (ms[0]) and the column-pass kernel (ms[1]) over the
+ * n_trips >= 1 trips; synchronises. */
+int lsr_time_kernels(lsr_plan p, void* E, void* Ninv, int n_trips, double* ms);
 
 /* Diagnostics of the state (E, Ninv); synchronises the stream. */
 int lsr_diag(lsr_plan p, const void* E, const void* Ninv, lsr_diag_out* out);
@@ -180,6 +186,18 @@ int lsr_batch_diag(lsr_batch b, int idx, const void* E, const void* Ninv,
 
 /* Set the trips per captured graph (k >= 1; 0 = no graph, eager launches). */
 int lsr_batch_set_graph_trips(lsr_batch b, int k);
+
+/* Launch configuration of a batch; a negative argument keeps the current
+ * value.  engine: 0 = one persistent kernel per round trip (task queue with
+ * per-cavity row-to-column dependencies), 1 = one grouped launch per pass
+ * (every cavity's row blocks, then every cavity's column blocks).  variant:
+ * register-budget variant of the kernels (0 = 2 waves/SIMD, 1 = 3).
+ * wgs_per_cu: resident workgroups per CU of the persistent kernel (0 =
+ * occupancy limit).  chunk: tickets taken per queue access.  lag: packer lag
+ * in row tasks.  graph_k: trips per captured graph (0 = eager).  cfg_out
+ * (nullable) receives the resulting six values in this order. */
+int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, int chunk,
+                        int lag, int graph_k, int* cfg_out);
 
 void lsr_batch_destroy(lsr_batch b);
 
@@ -222,8 +240,9 @@ int lsr_twiddle_table(int N, int prec, float* out, int capacity);
 /* The batch packer's task order for a set of grid sizes, host only:
  * writes per task (cavity index, kind 0 = row block / 1 = column block,
  * block index) triples to tasks (3 ints each) and returns the task count;
- * with tasks = NULL returns the count only.  lag = number of cavities whose
- * row tasks precede the column tasks of a cavity (-1 = default). */
+ * with tasks = NULL returns the count only.  The column tasks of a cavity
+ * follow once lag further row tasks have been issued after its last row task
+ * (-1 = default 2048).  Every column task's row tasks come before it. */
 int lsr_pack_tasks(const int* sizes, int count, int lag, int* tasks, int capacity);
 
 #ifdef __cplusplus

@@ -1,17 +1,636 @@
-// batch.hip -- placeholder until the persistent batched kernel lands.
+// batch.hip -- batched cavities: task packing, persistent-kernel launches,
+// HIP-graph replay of k round trips, autotuning with a JSON cache.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "batch.hpp"
 #include "host.hpp"
+
+namespace lsr {
+
+GroupInfo group_256();
+GroupInfo group_384();
+GroupInfo group_512();
+GroupInfo group_768();
+GroupInfo group_1024();
+GroupInfo group_2048();
+GroupInfo group_4096();
+GroupInfo group_small();
+GroupInfo group_all256();
+
+static const std::vector<GroupInfo>& groups() {
+    static const std::vector<GroupInfo> g = {group_256(),  group_384(),  group_512(),
+                                             group_768(),  group_1024(), group_2048(),
+                                             group_4096(), group_small(), group_all256()};
+    return g;
+}
+int group_count() { return (int)groups().size(); }
+const GroupInfo* group_at(int i) { return (i >= 0 && i < group_count()) ? &groups()[i] : nullptr; }
+
+int row_blocks(int N) {
+    ShapeInfo s;
+    if (!shape_for(N, false, &s)) return 0;
+    return N / s.LPW;
+}
+
+// Task order of one trip for cavities with the given row-block counts: all
+// row tasks in cavity order; the column tasks of cavity c follow once `lag`
+// further row tasks have been emitted after c's last row task (or at the
+// end).  Every column task therefore has a larger ticket than each row task
+// it depends on.
+static void pack(const std::vector<int>& nrb, int lag, bool with_cols, std::vector<int4>& out) {
+    out.clear();
+    const int n = (int)nrb.size();
+    std::vector<long> end(n);
+    long total = 0;
+    for (int c = 0; c < n; ++c) {
+        total += nrb[c];
+        end[c] = total;
+    }
+    int next_col = 0;
+    long emitted_rows = 0;
+    auto flush_cols = [&](bool all) {
+        while (with_cols && next_col < n && (all || end[next_col] + lag <= emitted_rows)) {
+            for (int b = 0; b < nrb[next_col]; ++b) out.push_back(int4{next_col, TASK_COL, b, 0});
+            ++next_col;
+        }
+    };
+    for (int c = 0; c < n; ++c)
+        for (int b = 0; b < nrb[c]; ++b) {
+            out.push_back(int4{c, TASK_ROW, b, 0});
+            ++emitted_rows;
+            flush_cols(false);
+        }
+    flush_cols(true);
+}
+
+static int default_lag() { return 2048; }
+
+struct Tune {
+    int engine = 1;       // 0 persistent kernel per trip, 1 grouped launch per pass
+    int variant = 0;      // kernel variant (register budget) of each group
+    int wgs_per_cu = 0;   // 0 = occupancy limit
+    int chunk = 2;
+    int lag = -1;         // -1 = default
+    int graph_k = 16;     // trips per captured graph; 0 = eager
+};
+
+// --------------------------------------------------------------- cache ----
+// {"<key>": {"wgs_per_cu": a, "chunk": b, "lag": c, "graph_k": d}, ...}
+static std::string cache_path(const char* p) {
+    if (p && *p) return p;
+    const char* e = getenv("LSR_TUNE_CACHE");
+    return e ? e : "";
+}
+
+static std::map<std::string, Tune> cache_read(const std::string& path) {
+    std::map<std::string, Tune> m;
+    if (path.empty()) return m;
+    FILE* f = fopen(path.c_str(), "rb");
+    if (!f) return m;
+    std::string s;
+    char buf[4096];
+    size_t k;
+    while ((k = fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, k);
+    fclose(f);
+    size_t i = 0;
+    while ((i = s.find('"', i)) != std::string::npos) {
+        const size_t j = s.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = s.substr(i + 1, j - i - 1);
+        const size_t ob = s.find('{', j), cb = s.find('}', j);
+        if (ob == std::string::npos || cb == std::string::npos || ob > cb) { i = j + 1; continue; }
+        const std::string body = s.substr(ob + 1, cb - ob - 1);
+        Tune t;
+        auto get = [&](const char* name, int& v) {
+            const std::string q = std::string("\"") + name + "\"";
+            const size_t p = body.find(q);
+            if (p != std::string::npos) {
+                const size_t c = body.find(':', p);
+                if (c != std::string::npos) v = atoi(body.c_str() + c + 1);
+            }
+        };
+        get("engine", t.engine);
+        get("variant", t.variant);
+        get("wgs_per_cu", t.wgs_per_cu);
+        get("chunk", t.chunk);
+        get("lag", t.lag);
+        get("graph_k", t.graph_k);
+        m[key] = t;
+        i = cb + 1;
+    }
+    return m;
+}
+
+static bool cache_write(const std::string& path, const std::map<std::string, Tune>& m) {
+    if (path.empty()) return true;
+    const std::string tmp = path + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "wb");
+    if (!f) return false;
+    fprintf(f, "{\n");
+    size_t n = 0;
+    for (const auto& kv : m) {
+        fprintf(f,
+                "  \"%s\": {\"engine\": %d, \"variant\": %d, \"wgs_per_cu\": %d, \"chunk\": %d, \"lag\": %d, "
+                "\"graph_k\": %d}%s\n",
+                kv.first.c_str(), kv.second.engine, kv.second.variant, kv.second.wgs_per_cu, kv.second.chunk,
+                kv.second.lag, kv.second.graph_k, ++n < m.size() ? "," : "");
+    }
+    fprintf(f, "}\n");
+    fclose(f);
+    return rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+}  // namespace lsr
 
 using namespace lsr;
 
+struct BatchGroup {
+    const GroupInfo* g = nullptr;
+    std::vector<int> cav;            // batch indices of this group's cavities
+    CavDesc* d_desc = nullptr;       // per cavity of the group
+    int4* d_tasks = nullptr;         // trip tasks (rows + columns)
+    int ntasks = 0;
+    int4* d_last = nullptr;          // row tasks only (last trip; grouped row pass)
+    int nlast = 0;
+    int4* d_cols = nullptr;          // column tasks only (grouped column pass)
+    int ncols = 0;
+    unsigned* d_ctrl = nullptr;
+    int occ[4] = {1, 1, 1, 1};   // resident workgroups per CU of each variant
+};
+
+struct lsr_batch_s {
+    int device = 0;
+    int cus = 256;
+    hipStream_t user = nullptr;      // stream of plans[0]
+    hipStream_t stream = nullptr;    // private stream (graph capture needs a non-null stream)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<lsr_plan> plans;
+    std::vector<BatchGroup> grp;
+    std::vector<void*> lastE, lastN;
+    Tune tune;
+    std::string key;
+    hipGraphExec_t graph = nullptr;
+    int graph_trips = 0;
+};
+
+static void batch_free(lsr_batch_s* b) {
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    for (auto& g : b->grp) {
+        if (g.d_desc) (void)hipFree(g.d_desc);
+        if (g.d_tasks) (void)hipFree(g.d_tasks);
+        if (g.d_last) (void)hipFree(g.d_last);
+        if (g.d_cols) (void)hipFree(g.d_cols);
+        if (g.d_ctrl) (void)hipFree(g.d_ctrl);
+    }
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+static std::string batch_key(const std::vector<lsr_plan>& plans) {
+    std::map<int, int> cnt;
+    for (auto* p : plans) cnt[p->N]++;
+    std::string k = "gfx950:batch:";
+    for (auto& kv : cnt) k += std::to_string(kv.first) + "x" + std::to_string(kv.second) + ";";
+    return k;
+}
+
+// (Re)build the task lists of every group for the current tuning.
+static int batch_pack(lsr_batch_s* b) {
+    const int lag = b->tune.lag >= 0 ? b->tune.lag : default_lag();
+    for (auto& g : b->grp) {
+        std::vector<int> nrb;
+        for (int c : g.cav) nrb.push_back(b->plans[c]->d.nrb);
+        std::vector<int4> t, l, cols;
+        pack(nrb, lag, true, t);
+        pack(nrb, 0, false, l);
+        for (const int4& x : t)
+            if (x.y == TASK_COL) cols.push_back(x);
+        if (g.d_tasks) (void)hipFree(g.d_tasks);
+        if (g.d_last) (void)hipFree(g.d_last);
+        if (g.d_cols) (void)hipFree(g.d_cols);
+        g.d_tasks = g.d_last = g.d_cols = nullptr;
+        if (hipMalloc(&g.d_tasks, t.size() * sizeof(int4)) != hipSuccess ||
+            hipMalloc(&g.d_last, l.size() * sizeof(int4)) != hipSuccess ||
+            hipMalloc(&g.d_cols, cols.size() * sizeof(int4)) != hipSuccess)
+            return set_err(LSR_ENOMEM, "task table allocation failed");
+        LSR_HIP(hipMemcpy(g.d_tasks, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
+        LSR_HIP(hipMemcpy(g.d_last, l.data(), l.size() * sizeof(int4), hipMemcpyHostToDevice));
+        LSR_HIP(hipMemcpy(g.d_cols, cols.data(), cols.size() * sizeof(int4), hipMemcpyHostToDevice));
+        g.ntasks = (int)t.size();
+        g.nlast = (int)l.size();
+        g.ncols = (int)cols.size();
+    }
+    return LSR_OK;
+}
+
+static int variant_of(const lsr_batch_s* b, const BatchGroup& g) {
+    const int v = b->tune.variant;
+    return (v >= 0 && v < g.g->nvariants) ? v : 0;
+}
+
+static int grid_of(const lsr_batch_s* b, const BatchGroup& g) {
+    int per_cu = g.occ[variant_of(b, g)];
+    if (b->tune.wgs_per_cu > 0 && b->tune.wgs_per_cu < per_cu) per_cu = b->tune.wgs_per_cu;
+    return per_cu * b->cus;
+}
+
+static int launch_trip(lsr_batch_s* b, int mode) {
+    if (b->tune.engine == 1) {
+        // grouped: every cavity's row blocks, then every cavity's column blocks
+        for (auto& g : b->grp) {
+            const KernelVariant& kv = g.g->var[variant_of(b, g)];
+            if (kv.launch_pass(mode, TASK_ROW, b->stream, g.d_desc, g.d_last, g.nlast))
+                return set_err(LSR_EDEVICE, "row-pass launch failed: %s", hipGetErrorString(hipGetLastError()));
+        }
+        if (mode != ROW_LAST)
+            for (auto& g : b->grp) {
+                const KernelVariant& kv = g.g->var[variant_of(b, g)];
+                if (kv.launch_pass(mode, TASK_COL, b->stream, g.d_desc, g.d_cols, g.ncols))
+                    return set_err(LSR_EDEVICE, "column-pass launch failed: %s",
+                                   hipGetErrorString(hipGetLastError()));
+            }
+        return LSR_OK;
+    }
+    for (auto& g : b->grp) {
+        const bool last = mode == ROW_LAST;
+        const int nt = last ? g.nlast : g.ntasks;
+        const int grid = std::min(grid_of(b, g), nt);
+        if (g.g->var[variant_of(b, g)].launch(mode, grid, b->stream, g.d_desc, last ? g.d_last : g.d_tasks, nt,
+                                              g.d_ctrl, last ? 1 : b->tune.chunk))
+            return set_err(LSR_EDEVICE, "persistent kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    return LSR_OK;
+}
+
+static void drop_graph(lsr_batch_s* b) {
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+    b->graph_trips = 0;
+}
+
+static int ensure_graph(lsr_batch_s* b, int k) {
+    if (b->graph && b->graph_trips == k) return LSR_OK;
+    drop_graph(b);
+    hipGraph_t gr = nullptr;
+    LSR_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int rc = LSR_OK;
+    for (int t = 0; t < k && rc == LSR_OK; ++t) rc = launch_trip(b, ROW_MID);
+    const hipError_t e = hipStreamEndCapture(b->stream, &gr);
+    if (rc != LSR_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return rc;
+    }
+    if (e != hipSuccess) return set_err(LSR_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    const hipError_t ie = hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (ie != hipSuccess) {
+        b->graph = nullptr;
+        return set_err(LSR_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
+    }
+    b->graph_trips = k;
+    return LSR_OK;
+}
+
+// Per-cavity descriptors: refreshed when the state pointers change.
+static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool force) {
+    bool same = !force && b->lastE.size() == b->plans.size();
+    for (size_t i = 0; same && i < b->plans.size(); ++i) same = b->lastE[i] == E[i] && b->lastN[i] == N[i];
+    if (same) return LSR_OK;
+    for (auto& g : b->grp) {
+        std::vector<CavDesc> h;
+        for (int c : g.cav) {
+            CavDesc d = b->plans[c]->d;
+            d.E = E[c];
+            d.Ninv = N[c];
+            h.push_back(d);
+        }
+        LSR_HIP(hipMemcpyAsync(g.d_desc, h.data(), h.size() * sizeof(CavDesc), hipMemcpyHostToDevice, b->stream));
+        LSR_HIP(hipStreamSynchronize(b->stream));
+    }
+    b->lastE.assign(E, E + b->plans.size());
+    b->lastN.assign(N, N + b->plans.size());
+    return LSR_OK;
+}
+
+static int run_trips(lsr_batch_s* b, int n) {
+    int rc = launch_trip(b, ROW_FIRST);
+    int left = n - 1;
+    const int k = b->tune.graph_k;
+    if (rc == LSR_OK && k > 0 && left >= k) {
+        rc = ensure_graph(b, k);
+        while (rc == LSR_OK && left >= k) {
+            if (hipGraphLaunch(b->graph, b->stream) != hipSuccess)
+                rc = set_err(LSR_EDEVICE, "graph launch failed: %s", hipGetErrorString(hipGetLastError()));
+            left -= k;
+        }
+    }
+    while (rc == LSR_OK && left > 0) {
+        rc = launch_trip(b, ROW_MID);
+        --left;
+    }
+    if (rc == LSR_OK) rc = launch_trip(b, ROW_LAST);
+    return rc;
+}
+
 extern "C" {
-int lsr_batch_create(lsr_batch* out, const lsr_plan*, int) {
-    if (out) *out = nullptr;
-    return set_err(LSR_EUNSUPPORTED, "batching not built yet");
+
+int lsr_pack_tasks(const int* sizes, int count, int lag, int* tasks, int capacity) {
+    if (!sizes || count < 1) return set_err(LSR_EINVAL, "no sizes");
+    std::vector<int> nrb;
+    for (int i = 0; i < count; ++i) {
+        const int r = row_blocks(sizes[i]);
+        if (!r) return set_err(LSR_EUNSUPPORTED, "N=%d is not compiled in", sizes[i]);
+        nrb.push_back(r);
+    }
+    std::vector<int4> t;
+    pack(nrb, lag >= 0 ? lag : default_lag(), true, t);
+    if (!tasks) return (int)t.size();
+    if (capacity < (int)t.size()) return set_err(LSR_EINVAL, "capacity %d < %zu tasks", capacity, t.size());
+    for (size_t i = 0; i < t.size(); ++i) {
+        tasks[3 * i] = t[i].x;
+        tasks[3 * i + 1] = t[i].y;
+        tasks[3 * i + 2] = t[i].z;
+    }
+    return (int)t.size();
 }
-int lsr_batch_roundtrips(lsr_batch, void* const*, void* const*, int) { return set_err(LSR_EUNSUPPORTED, "batching not built yet"); }
-int lsr_batch_diag(lsr_batch, int, const void*, const void*, lsr_diag_out*) { return set_err(LSR_EUNSUPPORTED, "batching not built yet"); }
-int lsr_batch_set_graph_trips(lsr_batch, int) { return set_err(LSR_EUNSUPPORTED, "batching not built yet"); }
-void lsr_batch_destroy(lsr_batch) {}
-int lsr_autotune(lsr_plan, lsr_batch, const char*) { return set_err(LSR_EUNSUPPORTED, "autotune not built yet"); }
-int lsr_pack_tasks(const int*, int, int, int*, int) { return set_err(LSR_EUNSUPPORTED, "batching not built yet"); }
+
+int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count) {
+    if (!out) return set_err(LSR_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!plans || count < 1) return set_err(LSR_EINVAL, "a batch needs at least one plan");
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i]) return set_err(LSR_EINVAL, "plan %d is NULL", i);
+        if (plans[i]->prec == PREC_FP64) return set_err(LSR_EUNSUPPORTED, "FP64 plans cannot be batched");
+        if (plans[i]->device != plans[0]->device) return set_err(LSR_EINVAL, "plans on different devices");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return set_err(LSR_EINVAL, "plan %d appears twice", i);
+    }
+    lsr_batch_s* b = new (std::nothrow) lsr_batch_s();
+    if (!b) return set_err(LSR_ENOMEM, "host allocation failed");
+    b->device = plans[0]->device;
+    DeviceGuard dg(b->device);
+    b->plans.assign(plans, plans + count);
+    b->user = plans[0]->stream;
+    auto fail = [&](int rc) {
+        batch_free(b);
+        delete b;
+        return rc;
+    };
+    if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
+        b->cus = 256;
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)
+        return fail(set_err(LSR_EDEVICE, "stream/event creation failed"));
+    // partition by workgroup size, pick the smallest compiled group per part
+    std::map<int, std::vector<int>> parts;
+    for (int i = 0; i < count; ++i) {
+        ShapeInfo s;
+        shape_for(plans[i]->N, false, &s);
+        parts[s.threads].push_back(i);
+    }
+    for (auto& kv : parts) {
+        const GroupInfo* best = nullptr;
+        for (int gi = 0; gi < group_count() && !best; ++gi) {
+            const GroupInfo* g = group_at(gi);
+            if (g->threads != kv.first) continue;
+            bool all = true;
+            for (int c : kv.second) {
+                bool in = false;
+                for (int k = 0; k < g->nsizes; ++k) in |= g->sizes[k] == plans[c]->N;
+                all &= in;
+            }
+            if (all) best = g;
+        }
+        if (!best) return fail(set_err(LSR_EUNSUPPORTED, "no compiled group covers this mix of sizes"));
+        BatchGroup bg;
+        bg.g = best;
+        bg.cav = kv.second;
+        for (int v = 0; v < best->nvariants; ++v) bg.occ[v] = best->var[v].occupancy();
+        const size_t ncav = bg.cav.size();
+        if (hipMalloc(&bg.d_desc, ncav * sizeof(CavDesc)) != hipSuccess ||
+            hipMalloc(&bg.d_ctrl, (CTRL_ROWDONE + ncav) * sizeof(unsigned)) != hipSuccess) {
+            b->grp.push_back(bg);
+            return fail(set_err(LSR_ENOMEM, "batch allocation failed"));
+        }
+        std::vector<unsigned> ctrl(CTRL_ROWDONE + ncav, 0u);
+        ctrl[CTRL_NCAV] = (unsigned)ncav;
+        b->grp.push_back(bg);
+        if (hipMemcpy(bg.d_ctrl, ctrl.data(), ctrl.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(set_err(LSR_EDEVICE, "control block upload failed"));
+    }
+    b->key = batch_key(b->plans);
+    auto cache = cache_read(cache_path(nullptr));
+    auto it = cache.find(b->key);
+    if (it != cache.end()) b->tune = it->second;
+    int rc = batch_pack(b);
+    if (rc) return fail(rc);
+    *out = b;
+    return LSR_OK;
 }
+
+int lsr_batch_set_graph_trips(lsr_batch b, int k) {
+    if (!b || k < 0) return set_err(LSR_EINVAL, "bad batch or k");
+    if (k != b->tune.graph_k) {
+        DeviceGuard dg(b->device);
+        drop_graph(b);
+        b->tune.graph_k = k;
+    }
+    return LSR_OK;
+}
+
+int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, int chunk, int lag, int graph_k,
+                        int* cfg_out) {
+    if (!b) return set_err(LSR_EINVAL, "batch is NULL");
+    if (engine > 1 || variant > 3 || chunk == 0 || chunk > 1024)
+        return set_err(LSR_EINVAL, "bad batch configuration");
+    DeviceGuard dg(b->device);
+    Tune t = b->tune;
+    if (engine >= 0) t.engine = engine;
+    if (variant >= 0) t.variant = variant;
+    if (wgs_per_cu >= 0) t.wgs_per_cu = wgs_per_cu;
+    if (chunk > 0) t.chunk = chunk;
+    if (lag >= 0) t.lag = lag;
+    if (graph_k >= 0) t.graph_k = graph_k;
+    const bool repack = t.lag != b->tune.lag;
+    drop_graph(b);
+    b->tune = t;
+    if (repack) {
+        LSR_HIP(hipStreamSynchronize(b->stream));
+        const int rc = batch_pack(b);
+        if (rc) return rc;
+    }
+    if (cfg_out) {
+        cfg_out[0] = t.engine;
+        cfg_out[1] = t.variant;
+        cfg_out[2] = t.wgs_per_cu;
+        cfg_out[3] = t.chunk;
+        cfg_out[4] = t.lag >= 0 ? t.lag : default_lag();
+        cfg_out[5] = t.graph_k;
+    }
+    return LSR_OK;
+}
+
+int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* N, int n_trips) {
+    if (!b) return set_err(LSR_EINVAL, "batch is NULL");
+    if (n_trips < 0) return set_err(LSR_EINVAL, "n_trips < 0");
+    if (!E || !N) return set_err(LSR_EINVAL, "E or Ninv array is NULL");
+    for (size_t i = 0; i < b->plans.size(); ++i)
+        if (!E[i] || !N[i] || ((uintptr_t)E[i] & 15u) || ((uintptr_t)N[i] & 15u))
+            return set_err(LSR_EINVAL, "state %zu: NULL or not 16-byte aligned", i);
+    if (n_trips == 0) return LSR_OK;
+    DeviceGuard dg(b->device);
+    // order after the caller's work on the plans' stream, and back
+    LSR_HIP(hipEventRecord(b->ev_in, b->user));
+    LSR_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    int rc = upload_descs(b, E, N, false);
+    if (rc == LSR_OK) rc = run_trips(b, n_trips);
+    LSR_HIP(hipEventRecord(b->ev_out, b->stream));
+    LSR_HIP(hipStreamWaitEvent(b->user, b->ev_out, 0));
+    if (rc) return rc;
+    for (auto* p : b->plans) {
+        p->trips_done += (unsigned long long)n_trips;
+        p->last_n = n_trips;
+    }
+    return LSR_OK;
+}
+
+int lsr_batch_diag(lsr_batch b, int idx, const void* E, const void* Ninv, lsr_diag_out* out) {
+    if (!b || idx < 0 || idx >= (int)b->plans.size()) return set_err(LSR_EINVAL, "bad batch or index");
+    return lsr_diag(b->plans[idx], E, Ninv, out);
+}
+
+void lsr_batch_destroy(lsr_batch b) {
+    if (!b) return;
+    DeviceGuard dg(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_free(b);
+    delete b;
+}
+
+// Time `trips` persistent trips (graph or eager per the tuning) on scratch
+// state; returns ms per trip or a negative status.
+static double time_batch(lsr_batch_s* b, const std::vector<void*>& E, const std::vector<void*>& N, int trips) {
+    if (upload_descs(b, E.data(), N.data(), false)) return -1;
+    if (run_trips(b, 2)) return -1;   // warm-up (also builds the graph)
+    hipEvent_t t0, t1;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return -1;
+    (void)hipEventRecord(t0, b->stream);
+    const int rc = run_trips(b, trips);
+    (void)hipEventRecord(t1, b->stream);
+    float ms = -1;
+    if (rc == 0 && hipEventSynchronize(t1) == hipSuccess) (void)hipEventElapsedTime(&ms, t0, t1);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return rc == 0 ? ms / trips : -1;
+}
+
+int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
+    if (!p && !b) return set_err(LSR_EINVAL, "nothing to tune");
+    if (p && !b) {
+        // one-cavity plans have one compiled shape per size: nothing to choose
+        return LSR_OK;
+    }
+    DeviceGuard dg(b->device);
+    LSR_HIP(hipStreamSynchronize(b->user));
+    // scratch state: zero fields (the kernels have no data-dependent paths)
+    std::vector<void*> E, N;
+    auto release = [&]() {
+        for (void* x : E) (void)hipFree(x);
+        for (void* x : N) (void)hipFree(x);
+    };
+    for (auto* q : b->plans) {
+        void *e = nullptr, *n = nullptr;
+        const size_t pts = (size_t)q->N * q->N;
+        if (hipMalloc(&e, pts * 8) != hipSuccess || hipMalloc(&n, pts * 4) != hipSuccess) {
+            if (e) (void)hipFree(e);
+            release();
+            return set_err(LSR_ENOMEM, "autotune scratch allocation failed");
+        }
+        (void)hipMemset(e, 0, pts * 8);
+        (void)hipMemset(n, 0, pts * 4);
+        E.push_back(e);
+        N.push_back(n);
+    }
+    const Tune saved = b->tune;
+    Tune best = saved;
+    double best_ms = 1e30;
+    long pts_total = 0;
+    for (auto* q : b->plans) pts_total += (long)q->N * q->N;
+    const int trips = pts_total > 32L * 1024 * 1024 ? 6 : 24;
+    int nvar = 1;
+    for (auto& g : b->grp) nvar = std::max(nvar, g.g->nvariants);
+    // grouped launches: the register budget is the only choice
+    for (int v = 0; v < nvar; ++v) {
+        b->tune.engine = 1;
+        b->tune.variant = v;
+        b->tune.graph_k = 16;
+        drop_graph(b);
+        if (batch_pack(b)) continue;
+        const double ms = time_batch(b, E, N, trips);
+        if (ms > 0 && ms < best_ms) {
+            best_ms = ms;
+            best = b->tune;
+        }
+    }
+    for (int v = 0; v < nvar; ++v) {
+        int occ = 1;
+        for (auto& g : b->grp) occ = std::max(occ, g.occ[v < g.g->nvariants ? v : 0]);
+        std::vector<int> wgs;
+        for (int w = occ; w >= 1 && (int)wgs.size() < 3; --w) wgs.push_back(w);
+        for (int w : wgs)
+            for (int chunk : {1, 2, 4, 8})
+                for (int lag : {512, 2048, 8192}) {
+                b->tune.engine = 0;
+                b->tune.variant = v;
+                b->tune.wgs_per_cu = w;
+                b->tune.chunk = chunk;
+                b->tune.lag = lag;
+                b->tune.graph_k = 16;
+                drop_graph(b);
+                if (batch_pack(b)) continue;
+                const double ms = time_batch(b, E, N, trips);
+                if (ms > 0 && ms < best_ms) {
+                    best_ms = ms;
+                    best = b->tune;
+                }
+                }
+    }
+    for (int k : {0, 4, 16, 64}) {
+        b->tune = best;
+        b->tune.graph_k = k;
+        drop_graph(b);
+        if (batch_pack(b)) continue;
+        const double ms = time_batch(b, E, N, std::max(trips, k + 1));
+        if (ms > 0 && ms < best_ms * 0.995) {
+            best_ms = ms;
+            best = b->tune;
+        }
+    }
+    (void)hipStreamSynchronize(b->stream);
+    release();
+    b->tune = best;
+    drop_graph(b);
+    b->lastE.clear();
+    b->lastN.clear();
+    int rc = batch_pack(b);
+    if (rc) return rc;
+    if (best_ms >= 1e30) return set_err(LSR_EDEVICE, "autotune: no candidate ran");
+    const std::string cp = cache_path(path);
+    if (!cp.empty()) {
+        auto cache = cache_read(cp);
+        cache[b->key] = best;
+        if (!cache_write(cp, cache)) return set_err(LSR_EINVAL, "cannot write tune cache %s", cp.c_str());
+    }
+    return LSR_OK;
+}
+
+}  // extern "C"

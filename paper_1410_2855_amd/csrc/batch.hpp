@@ -1,0 +1,41 @@
+// batch.hpp -- shared definitions of the batched (persistent-kernel) path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "desc.hpp"
+
+namespace lsr {
+
+enum : int { TASK_ROW = 0, TASK_COL = 1 };
+
+// Control block of a group (device, unsigned words).
+enum : int { CTRL_HEAD = 0, CTRL_EXIT = 1, CTRL_NCAV = 2, CTRL_ABORT = 3, CTRL_ROWDONE = 16 };
+
+struct KernelVariant {
+    // persistent kernel: one launch per round trip
+    int (*launch)(int mode, int grid, hipStream_t st, const CavDesc* descs, const int4* tasks, int ntasks,
+                  unsigned* ctrl, int chunk);
+    // grouped launch: one launch per pass, one workgroup per task
+    int (*launch_pass)(int mode, int kind, hipStream_t st, const CavDesc* descs, const int4* tasks, int ntasks);
+    int (*occupancy)();
+    int waves_per_eu;    // register budget the variant was compiled for
+};
+
+struct GroupInfo {
+    int threads;
+    int nsizes;
+    int sizes[8];
+    int nvariants;
+    KernelVariant var[4];
+};
+
+// Compiled groups, smallest first; the batch picks, for its sizes, the
+// first group that contains all of them (per workgroup size).
+int group_count();
+const GroupInfo* group_at(int i);
+
+// Row blocks per cavity of size N in the FP32 shapes (0 if unsupported).
+int row_blocks(int N);
+
+}  // namespace lsr

@@ -1,0 +1,187 @@
+// batch_impl.hpp -- one persistent kernel per round trip for many cavities.
+//
+// All cavities of a group advance one round trip per launch.  The work of a
+// trip is a list of tasks (row blocks and column blocks of every cavity),
+// ordered by the host packer so that a cavity's column tasks come after all
+// of its row tasks.  Workgroups take tickets from an atomic queue in chunks
+// and run the tasks in ticket order; a column task first waits until its
+// cavity's row-done counter reaches the number of row blocks (release on the
+// producer side, acquire on the consumer side, both at device scope since
+// the eight XCDs have separate L2 caches).  Because a column task only ever
+// waits on tickets smaller than its own, which running workgroups hold and
+// finish without waiting, the queue cannot deadlock for any grid size.  The
+// wait is still bounded: after ~2 s it raises an abort flag that releases
+// every waiter, and the cavity's counters report the failure to the host.  The
+// last workgroup to leave resets the queue head and the counters, so the same
+// launch can be replayed from a HIP graph.
+#pragma once
+
+#include <initializer_list>
+
+#include "batch.hpp"
+#include "map.hpp"
+
+namespace lsr {
+
+// Sizes sharing one persistent kernel: same workgroup size; the LDS buffer
+// is the largest of their line buffers.
+template <class S0, class... Ss>
+struct Group {
+    static constexpr int THREADS = S0::THREADS;
+    static_assert(((Ss::THREADS == THREADS) && ...), "one group, one workgroup size");
+    static constexpr int maxl() {
+        int m = S0::LDS_ELEMS * 8;
+        ((m = m > Ss::LDS_ELEMS * 8 ? m : Ss::LDS_ELEMS * 8), ...);
+        return m;
+    }
+};
+
+template <int MODE, class S>
+__device__ __forceinline__ bool run_if(const CavDesc& d, int kind, int blk, unsigned char* smem, double* red) {
+    if (d.N != S::N) return false;
+    cx<float>* lds = reinterpret_cast<cx<float>*>(smem);
+    if (kind == TASK_ROW) row_task<S, float, MODE>(d, blk, lds, red);
+    else col_task<S, float, COL_PROP>(d, blk, lds);
+    return true;
+}
+
+// WPE: waves per SIMD the register allocation must allow (2 leaves 256
+// VGPRs, 3 leaves 168); the autotuner picks the faster variant.
+template <int MODE, int THREADS, int LDS_BYTES, int WPE, class... Ss>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_trip(const CavDesc* __restrict__ descs,
+                                                  const int4* __restrict__ tasks, int ntasks,
+                                                  unsigned* __restrict__ ctrl, int chunk) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
+    __shared__ double red[4 * 16];
+    __shared__ int s_ticket;
+    unsigned* head = ctrl + CTRL_HEAD;
+    unsigned* done = ctrl + CTRL_ROWDONE;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_ticket = (int)__hip_atomic_fetch_add(head, (unsigned)chunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int t0 = __builtin_amdgcn_readfirstlane(s_ticket);
+        if (t0 >= ntasks) break;
+        const int t1 = t0 + chunk < ntasks ? t0 + chunk : ntasks;
+        for (int t = t0; t < t1; ++t) {
+            const int4 tk = tasks[t];
+            const int cav = __builtin_amdgcn_readfirstlane(tk.x);
+            const int kind = __builtin_amdgcn_readfirstlane(tk.y);
+            const int blk = __builtin_amdgcn_readfirstlane(tk.z);
+            const CavDesc& d = descs[cav];
+            if (kind == TASK_COL) {
+                if (threadIdx.x == 0) {
+                    // bounded wait: a dependency that never completes (a bad task
+                    // table) marks the cavity failed and releases its waiters
+                    const unsigned need = (unsigned)d.nrb;
+                    unsigned spins = 0;
+                    while (__hip_atomic_load(done + cav, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        if (__hip_atomic_load(ctrl + CTRL_ABORT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                        __builtin_amdgcn_s_sleep(2);
+                        if (++spins > (1u << 25)) {   // ~2 s
+                            __hip_atomic_store(ctrl + CTRL_ABORT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            d.counters[CNT_HANG] = 1u;
+                            break;
+                        }
+                    }
+                }
+                // one acquire suffices: it invalidates this CU's L1 and this
+                // XCD's L2, which every wave of the workgroup reads through
+                if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __syncthreads();
+                if (blk == 0 && threadIdx.x < 64) finalize_sums(d);
+            }
+            (run_if<MODE, Ss>(d, kind, blk, smem, red) || ...);
+            if (kind == TASK_ROW) {
+                // each wave waits for its stores to reach L2; after the
+                // barrier one device-scope release writes the XCD's L2 back
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    __hip_atomic_fetch_add(done + cav, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        const unsigned old = __hip_atomic_fetch_add(ctrl + CTRL_EXIT, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == gridDim.x - 1) {
+            const int ncav = (int)ctrl[CTRL_NCAV];
+            for (int c = 0; c < ncav; ++c) done[c] = 0u;
+            ctrl[CTRL_HEAD] = 0u;
+            ctrl[CTRL_ABORT] = 0u;
+            ctrl[CTRL_EXIT] = 0u;
+        }
+    }
+}
+
+// Grouped launch: one workgroup per task of one pass (all row blocks, or
+// all column blocks, of every cavity); the kernel boundary orders the passes.
+template <int MODE, int KIND, int THREADS, int LDS_BYTES, int WPE, class... Ss>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_pass(
+    const CavDesc* __restrict__ descs, const int4* __restrict__ tasks) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
+    __shared__ double red[4 * 16];
+    const int4 tk = tasks[blockIdx.x];
+    const int cav = __builtin_amdgcn_readfirstlane(tk.x);
+    const int blk = __builtin_amdgcn_readfirstlane(tk.z);
+    const CavDesc& d = descs[cav];
+    if constexpr (KIND == TASK_COL) {
+        if (blk == 0 && threadIdx.x < 64) finalize_sums(d);
+    }
+    (run_if<MODE, Ss>(d, KIND, blk, smem, red) || ...);
+}
+
+template <int WPE, class... Ss>
+struct GroupKernels {
+    static constexpr int THREADS = Group<Ss...>::THREADS;
+    static constexpr int LDS = Group<Ss...>::maxl();
+
+    static int launch(int mode, int grid, hipStream_t st, const CavDesc* descs, const int4* tasks,
+                      int ntasks, unsigned* ctrl, int chunk) {
+        const dim3 g(grid), b(THREADS);
+        switch (mode) {
+        case ROW_FIRST: hipLaunchKernelGGL((k_trip<ROW_FIRST, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks, ctrl, chunk); break;
+        case ROW_MID:   hipLaunchKernelGGL((k_trip<ROW_MID, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks, ctrl, chunk); break;
+        case ROW_LAST:  hipLaunchKernelGGL((k_trip<ROW_LAST, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks, ctrl, chunk); break;
+        default: return -1;
+        }
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+    }
+    static int occupancy() {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trip<ROW_MID, THREADS, LDS, WPE, Ss...>, THREADS, 0) != hipSuccess)
+            return 1;
+        return n > 0 ? n : 1;
+    }
+    // grouped launch of one pass: grid = number of tasks of that pass
+    static int launch_pass(int mode, int kind, hipStream_t st, const CavDesc* descs, const int4* tasks,
+                           int ntasks) {
+        const dim3 g(ntasks), b(THREADS);
+        if (kind == TASK_COL) {
+            hipLaunchKernelGGL((k_pass<ROW_MID, TASK_COL, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks);
+        } else {
+            switch (mode) {
+            case ROW_FIRST: hipLaunchKernelGGL((k_pass<ROW_FIRST, TASK_ROW, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks); break;
+            case ROW_MID:   hipLaunchKernelGGL((k_pass<ROW_MID, TASK_ROW, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks); break;
+            case ROW_LAST:  hipLaunchKernelGGL((k_pass<ROW_LAST, TASK_ROW, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks); break;
+            default: return -1;
+            }
+        }
+        return hipGetLastError() == hipSuccess ? 0 : -3;
+    }
+    static KernelVariant variant() { return KernelVariant{&launch, &launch_pass, &occupancy, WPE}; }
+};
+
+template <class... Ss>
+GroupInfo group_info(std::initializer_list<KernelVariant> vars) {
+    GroupInfo gi{};
+    gi.threads = Group<Ss...>::THREADS;
+    gi.nsizes = 0;
+    ((gi.sizes[gi.nsizes++] = Ss::N), ...);
+    gi.nvariants = 0;
+    for (const KernelVariant& v : vars) gi.var[gi.nvariants++] = v;
+    return gi;
+}
+
+}  // namespace lsr

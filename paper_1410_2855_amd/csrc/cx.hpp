@@ -18,9 +18,15 @@ template <typename T>
 __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
 template <typename T>
 __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+// The library is compiled with -ffp-contract=off, so every rounding is the one
+// written here: fused multiply-adds are explicit.  This keeps a split run
+// (trip kernels launched separately) bitwise equal to a continuous one.
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fma_(a.re, b.re, -(a.im * b.im)), fma_(a.re, b.im, a.im * b.re)};
 }
 template <typename T>
 __device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }

@@ -18,7 +18,8 @@ enum ColMode : int { COL_PROP = 0, COL_DIAG = 1 };
 // Counters of a cavity (device, 16 words):
 //  [0] trips completed (trace ring slot of the next trip)
 //  [1] first trip (1-based) whose sums were non-finite, 0 if none
-enum : int { CNT_TRIPS = 0, CNT_NONFINITE = 1, CNT_WORDS = 16 };
+//  [2] set when a batched column task gave up waiting for its row pass
+enum : int { CNT_TRIPS = 0, CNT_NONFINITE = 1, CNT_HANG = 2, CNT_WORDS = 16 };
 
 struct CavDesc {
     void* E;                // field (row-major between calls, tiled inside)

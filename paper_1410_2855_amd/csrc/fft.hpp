@@ -52,7 +52,7 @@ __device__ __forceinline__ cx<T> twc(cx<T> a) {
         constexpr double th = 2.0 * kPi * m / R;
         constexpr T c = (T)ce_cos(th);
         constexpr T s = (T)(DIR * ce_sin(th));
-        return {a.re * c - a.im * s, a.re * s + a.im * c};
+        return {fma_(a.re, c, -(a.im * s)), fma_(a.re, s, a.im * c)};
     }
 }
 
@@ -69,7 +69,7 @@ __device__ __forceinline__ void dft(cx<T>* x) {
         constexpr T s3 = (T)0.86602540378443864676372317075293618;
         cx<T> t = x[1] + x[2];
         cx<T> d = scale(rot_q<DIR>(x[1] - x[2]), s3);
-        cx<T> m = {x[0].re - (T)0.5 * t.re, x[0].im - (T)0.5 * t.im};
+        cx<T> m = {fma_((T)-0.5, t.re, x[0].re), fma_((T)-0.5, t.im, x[0].im)};
         x[0] = x[0] + t;
         x[1] = m + d;
         x[2] = m - d;

@@ -55,6 +55,15 @@ __device__ __forceinline__ void sc(double x, double* s, double* c) { sincos(x, s
 
 __device__ __forceinline__ int signed_idx(int q, int n) { return (2 * q < n) ? q : q - n; }
 
+// threadIdx.x hidden from loop-invariant code motion: in the persistent
+// kernel every lane-dependent address would otherwise be hoisted out of the
+// task loop and held in registers across all tasks.
+__device__ __forceinline__ int opaque_tid() {
+    int t = (int)threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // round(sqrt(s)) for an integer s >= 0, exactly: k with k^2 - k < s <= k^2 + k.
 __device__ __forceinline__ int round_sqrt(int s) {
     int k = (int)(sqrtf((float)s) + 0.5f);
@@ -81,18 +90,18 @@ __device__ __forceinline__ void row_chunk_pos(int c, int& l, int& x) {
 }
 
 template <class S, typename T, int LAYOUT>
-__device__ __forceinline__ void stage_in_rows(const cx<T>* __restrict__ blk, cx<T>* lds) {
+__device__ __forceinline__ void stage_in_rows(const cx<T>* __restrict__ blk, cx<T>* lds, int tid) {
     using V = typename V16<T>::type;
     constexpr int NCH = S::LPW * S::N / EPC<T>;
     static_assert(NCH % S::THREADS == 0, "row staging must tile the workgroup");
     constexpr int IT = NCH / S::THREADS;
     const V* src = reinterpret_cast<const V*>(blk);
     V q[IT];
-    sfor<0, IT>([&](auto ic) { q[decltype(ic)::value] = src[threadIdx.x + decltype(ic)::value * S::THREADS]; });
+    sfor<0, IT>([&](auto ic) { q[decltype(ic)::value] = src[tid + decltype(ic)::value * S::THREADS]; });
     sfor<0, IT>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         int l, x;
-        row_chunk_pos<S, T, LAYOUT>(threadIdx.x + i * S::THREADS, l, x);
+        row_chunk_pos<S, T, LAYOUT>(tid + i * S::THREADS, l, x);
         cx<T> e[EPC<T>];
         unpack16<T>(q[i], e);
         sfor<0, EPC<T>>([&](auto kc) { lds[l * S::LINE + S::pad(x + decltype(kc)::value)] = e[decltype(kc)::value]; });
@@ -100,14 +109,14 @@ __device__ __forceinline__ void stage_in_rows(const cx<T>* __restrict__ blk, cx<
 }
 
 template <class S, typename T, int LAYOUT>
-__device__ __forceinline__ void stage_out_rows(cx<T>* __restrict__ blk, const cx<T>* lds) {
+__device__ __forceinline__ void stage_out_rows(cx<T>* __restrict__ blk, const cx<T>* lds, int tid) {
     using V = typename V16<T>::type;
     constexpr int NCH = S::LPW * S::N / EPC<T>;
     constexpr int IT = NCH / S::THREADS;
     V* dst = reinterpret_cast<V*>(blk);
     sfor<0, IT>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        const int c = threadIdx.x + i * S::THREADS;
+        const int c = tid + i * S::THREADS;
         int l, x;
         row_chunk_pos<S, T, LAYOUT>(c, l, x);
         cx<T> e[EPC<T>];
@@ -129,7 +138,7 @@ __device__ __forceinline__ size_t col_chunk(int c, int cb, int& line, int& y) {
 }
 
 template <class S, typename T>
-__device__ __forceinline__ void stage_in_cols(const cx<T>* __restrict__ E, int cb, cx<T>* lds) {
+__device__ __forceinline__ void stage_in_cols(const cx<T>* __restrict__ E, int cb, cx<T>* lds, int tid) {
     using V = typename V16<T>::type;
     static_assert(S::LPW % EPC<T> == 0, "a chunk must stay inside one tile row");
     constexpr int NCH = S::N * S::LPW / EPC<T>;
@@ -141,7 +150,7 @@ __device__ __forceinline__ void stage_in_cols(const cx<T>* __restrict__ E, int c
     int ln[IT], yy[IT];
     sfor<0, IT>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        off[i] = col_chunk<S, T>(threadIdx.x + i * S::THREADS, cb, ln[i], yy[i]);
+        off[i] = col_chunk<S, T>(tid + i * S::THREADS, cb, ln[i], yy[i]);
     });
     sfor<0, IT>([&](auto ic) { q[decltype(ic)::value] = src[off[decltype(ic)::value]]; });
     sfor<0, IT>([&](auto ic) {
@@ -156,7 +165,7 @@ __device__ __forceinline__ void stage_in_cols(const cx<T>* __restrict__ E, int c
 }
 
 template <class S, typename T>
-__device__ __forceinline__ void stage_out_cols(cx<T>* __restrict__ E, int cb, const cx<T>* lds) {
+__device__ __forceinline__ void stage_out_cols(cx<T>* __restrict__ E, int cb, const cx<T>* lds, int tid) {
     using V = typename V16<T>::type;
     constexpr int NCH = S::N * S::LPW / EPC<T>;
     constexpr int IT = NCH / S::THREADS;
@@ -164,7 +173,7 @@ __device__ __forceinline__ void stage_out_cols(cx<T>* __restrict__ E, int cb, co
     sfor<0, IT>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         int line, y;
-        const size_t off = col_chunk<S, T>(threadIdx.x + i * S::THREADS, cb, line, y);
+        const size_t off = col_chunk<S, T>(tid + i * S::THREADS, cb, line, y);
         cx<T> e[EPC<T>];
         sfor<0, EPC<T>>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
@@ -183,9 +192,8 @@ __device__ __forceinline__ double wave_sum(double x) {
 }
 
 template <class S>
-__device__ __forceinline__ void block_sums_store(double* acc, double* red, double* out) {
+__device__ __forceinline__ void block_sums_store(double* acc, double* red, double* out, int tid) {
     constexpr int NW = S::THREADS / 64;
-    const int tid = threadIdx.x;
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = wave_sum(acc[q]);
     if ((tid & 63) == 0) {
@@ -251,7 +259,7 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
             const int x = reg_pos<S, R>(lane, b, r);
             const cx<T> e = v[b * R + r];
             const T n = nv[b * R + r];
-            const T I = norm2(e);
+            const T I = fma_(e.re, e.re, e.im * e.im);
             T A = (T)1;
             if (kind == AP_MASK) {
                 A = mask[(size_t)y * S::N + x];
@@ -274,8 +282,8 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
             if (foc) g = cmul(g, cmul(foc[x], fy));
             v[b * R + r] = g;
             if constexpr (MODE != ROW_DIAG) {
-                const T pump = pc ? N0 * ((T)1 + mamp * pc[x] * pcy) : N0;
-                ninv[(size_t)y * S::N + x] = n + (pump - n) * iT1 - n * I;
+                const T pump = pc ? N0 * fma_(mamp * pc[x], pcy, (T)1) : N0;
+                ninv[(size_t)y * S::N + x] = fma_(-n, I, fma_(pump - n, iT1, n));
             }
         });
     });
@@ -284,7 +292,7 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
 // ---------------------------------------------------------------------------
 template <class S, typename T, int MODE>
 __device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, double* red) {
-    const int tid = threadIdx.x;
+    const int tid = opaque_tid();
     const int line = tid / S::L, lane = tid % S::L;
     const int y = rb * S::LPW + line;
     cx<T>* blk = static_cast<cx<T>*>(d.E) + (size_t)rb * S::LPW * S::N;
@@ -303,8 +311,8 @@ __device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, d
             });
         });
     }
-    if constexpr (MODE == ROW_FIRST || MODE == ROW_DIAG) stage_in_rows<S, T, 0>(blk, lds);
-    else stage_in_rows<S, T, 1>(blk, lds);
+    if constexpr (MODE == ROW_FIRST || MODE == ROW_DIAG) stage_in_rows<S, T, 0>(blk, lds, tid);
+    else stage_in_rows<S, T, 1>(blk, lds, tid);
     __syncthreads();
 
     cx<T> v[S::P];
@@ -319,24 +327,24 @@ __device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, d
     if constexpr (MODE == ROW_LAST) {
         scatter_out<S, RF>(v, myl, lane);
         __syncthreads();
-        stage_out_rows<S, T, 0>(blk, lds);
+        stage_out_rows<S, T, 0>(blk, lds, tid);
         return;
     } else {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         local_step<S, T, MODE>(v, nv, d, y, lane, acc);
-        block_sums_store<S>(acc, red, d.partials + 4 * rb);
+        block_sums_store<S>(acc, red, d.partials + 4 * rb, tid);
         fft_line<S, FWD>(v, myl, lane, tw);
         scatter_out<S, RL>(v, myl, lane);
         __syncthreads();
         cx<T>* dst = blk;
         if constexpr (MODE == ROW_DIAG) dst = static_cast<cx<T>*>(d.scratch) + (size_t)rb * S::LPW * S::N;
-        stage_out_rows<S, T, 1>(dst, lds);
+        stage_out_rows<S, T, 1>(dst, lds, tid);
     }
 }
 
 template <class S, typename T, int MODE>
 __device__ __forceinline__ void col_task(const CavDesc& d, int cb, cx<T>* lds) {
-    const int tid = threadIdx.x;
+    const int tid = opaque_tid();
     const int line = tid / S::L, lane = tid % S::L;
     cx<T>* E = static_cast<cx<T>*>(MODE == COL_DIAG ? d.scratch : d.E);
     const cx<T>* tw = static_cast<const cx<T>*>(d.tw);
@@ -345,7 +353,7 @@ __device__ __forceinline__ void col_task(const CavDesc& d, int cb, cx<T>* lds) {
     constexpr int RL = R_LAST<S>;
     constexpr int B = S::P / RL;
 
-    stage_in_cols<S, T>(E, cb, lds);
+    stage_in_cols<S, T>(E, cb, lds, tid);
     __syncthreads();
     cx<T> v[S::P];
     gather_in<S, RF>(v, myl, lane);
@@ -398,7 +406,7 @@ __device__ __forceinline__ void col_task(const CavDesc& d, int cb, cx<T>* lds) {
         fft_line<S, INV>(v, myl, lane, tw);
         scatter_out<S, RF>(v, myl, lane);
         __syncthreads();
-        stage_out_cols<S, T>(E, cb, lds);
+        stage_out_cols<S, T>(E, cb, lds, tid);
     }
 }
 

@@ -372,12 +372,75 @@ int lsr_roundtrips(lsr_plan p, void* E, void* Ninv, int n_trips) {
     return LSR_OK;
 }
 
+int lsr_time_kernels(lsr_plan p, void* E, void* Ninv, int n_trips, double* ms) {
+    if (!p || !ms) return set_err(LSR_EINVAL, "plan or ms is NULL");
+    if (n_trips < 1) return set_err(LSR_EINVAL, "n_trips < 1");
+    if (!E || !Ninv || !aligned16(E) || !aligned16(Ninv)) return set_err(LSR_EINVAL, "bad E/Ninv pointer");
+    DeviceGuard g(p->device);
+    CavDesc d = p->d;
+    d.E = E;
+    d.Ninv = Ninv;
+    const Launchers* k = p->kern;
+    const int nl = 2 * n_trips + 1;
+    std::vector<hipEvent_t> ev(2 * (size_t)nl, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& x : ev)
+                if (x) (void)hipEventDestroy(x);
+            return set_err(LSR_EDEVICE, "hipEventCreate failed");
+        }
+    int rc = 0, li = 0;
+    auto launch = [&](bool row, int mode) {
+        (void)hipEventRecord(ev[2 * li], p->stream);
+        if (rc == 0) rc = row ? k->row(d, mode, p->stream) : k->col(d, mode, p->stream);
+        (void)hipEventRecord(ev[2 * li + 1], p->stream);
+        ++li;
+    };
+    launch(true, ROW_FIRST);
+    for (int t = 0; t < n_trips; ++t) {
+        launch(false, COL_PROP);
+        launch(true, t + 1 < n_trips ? ROW_MID : ROW_LAST);
+    }
+    double row_ms = 0, col_ms = 0;
+    int nrow = 0, ncol = 0;
+    if (rc == 0 && hipStreamSynchronize(p->stream) == hipSuccess) {
+        // launch order: row, (col, row) * n; the first and last row launches
+        // (FIRST / LAST forms) are excluded from the row mean when n > 1
+        for (int i = 0; i < nl; ++i) {
+            float t = 0;
+            (void)hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+            const bool row = (i % 2) == 0;
+            if (row) {
+                if (n_trips > 1 && (i == 0 || i == nl - 1)) continue;
+                row_ms += t;
+                ++nrow;
+            } else {
+                col_ms += t;
+                ++ncol;
+            }
+        }
+    } else if (rc == 0) {
+        rc = -3;
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    if (rc != 0) return set_err(LSR_EDEVICE, "timed launches failed: %s", hipGetErrorString(hipGetLastError()));
+    ms[0] = nrow ? row_ms / nrow : 0.0;
+    ms[1] = ncol ? col_ms / ncol : 0.0;
+    p->trips_done += (unsigned long long)n_trips;
+    p->last_n = n_trips;
+    return LSR_OK;
+}
+
 int lsr_sync(lsr_plan p) {
     if (!p) return set_err(LSR_EINVAL, "plan is NULL");
     DeviceGuard g(p->device);
     LSR_HIP(hipStreamSynchronize(p->stream));
     unsigned c[CNT_WORDS];
     LSR_HIP(hipMemcpy(c, p->d_counters, sizeof c, hipMemcpyDeviceToHost));
+    if (c[CNT_HANG]) {
+        LSR_HIP(hipMemset(p->d_counters + CNT_HANG, 0, sizeof(unsigned)));
+        return set_err(LSR_EDEVICE, "a batched round trip gave up waiting for its row pass (task table error)");
+    }
     if (c[CNT_NONFINITE]) {
         const unsigned bad = c[CNT_NONFINITE];
         LSR_HIP(hipMemset(p->d_counters + CNT_NONFINITE, 0, sizeof(unsigned)));

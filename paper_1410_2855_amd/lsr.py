@@ -53,6 +53,7 @@ _SIGS = {
     "lsr_plan_set_stream": (_i, [_vp, _vp]),
     "lsr_roundtrips": (_i, [_vp, _vp, _vp, _i]),
     "lsr_sync": (_i, [_vp]),
+    "lsr_time_kernels": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d)]),
     "lsr_trace": (_i, [_vp, ctypes.POINTER(_d), _i]),
     "lsr_diag": (_i, [_vp, _vp, _vp, ctypes.POINTER(lsr_diag_out)]),
     "lsr_plan_nbins": (_i, [_vp]),
@@ -61,6 +62,7 @@ _SIGS = {
     "lsr_batch_roundtrips": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i]),
     "lsr_batch_diag": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(lsr_diag_out)]),
     "lsr_batch_set_graph_trips": (_i, [_vp, _i]),
+    "lsr_batch_configure": (_i, [_vp, _i, _i, _i, _i, _i, _i, ctypes.POINTER(_i)]),
     "lsr_batch_destroy": (None, [_vp]),
     "lsr_autotune": (_i, [_vp, _vp, ctypes.c_char_p]),
     "lsr_last_error": (ctypes.c_char_p, []),
@@ -176,6 +178,13 @@ def lsr_roundtrips(plan, E, Ninv, n_trips: int):
     _check(load().lsr_roundtrips(plan, _ptr(E), _ptr(Ninv), n_trips))
 
 
+def lsr_time_kernels(plan, E, Ninv, n_trips: int):
+    """Mean (row-pass ms, column-pass ms) over n_trips event-bracketed trips."""
+    ms = (ctypes.c_double * 2)()
+    _check(load().lsr_time_kernels(plan, _ptr(E), _ptr(Ninv), n_trips, ms))
+    return ms[0], ms[1]
+
+
 def lsr_sync(plan):
     _check(load().lsr_sync(plan))
 
@@ -233,6 +242,12 @@ def lsr_batch_diag(batch, idx: int, E, Ninv, nbins: int) -> dict:
 
 def lsr_batch_set_graph_trips(batch, k: int):
     _check(load().lsr_batch_set_graph_trips(batch, k))
+
+
+def lsr_batch_configure(batch, engine=-1, variant=-1, wgs_per_cu=-1, chunk=-1, lag=-1, graph_k=-1) -> dict:
+    out = (ctypes.c_int * 6)()
+    _check(load().lsr_batch_configure(batch, engine, variant, wgs_per_cu, chunk, lag, graph_k, out))
+    return dict(zip(("engine", "variant", "wgs_per_cu", "chunk", "lag", "graph_k"), out[:]))
 
 
 def lsr_batch_destroy(batch):

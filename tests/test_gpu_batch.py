@@ -1,0 +1,144 @@
+"""Batched path (persistent kernel per round trip, HIP graph of k trips)
+against the one-cavity path and the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1410_2855_amd.inputs import Cavity, initial_state, oracle_params, sweep
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1410_2855_amd import lsr  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def make(cavs):
+    plans, Es, Ns = [], [], []
+    for c in cavs:
+        p = lsr.Plan(c)
+        e, n = p.state(*initial_state(c))
+        plans.append(p)
+        Es.append(e)
+        Ns.append(n)
+    return plans, Es, Ns
+
+
+def plain_reference(cavs, trips):
+    plans, Es, Ns = make(cavs)
+    for p, e, n in zip(plans, Es, Ns):
+        p.roundtrips(e, n, trips)
+    traces = [p.trace(trips) for p in plans]
+    for p in plans:
+        p.sync()
+    out = [(e.clone(), n.clone()) for e, n in zip(Es, Ns)]
+    for p in plans:
+        p.close()
+    return out, traces
+
+
+def mixed(count, sizes):
+    cavs = sweep(count, seed=3, sizes=sizes)
+    return cavs
+
+
+@pytest.mark.parametrize("sizes,count,trips,k", [
+    ((256, 384, 512, 768, 1024), 9, 13, 4),     # mixed group, graph + remainder
+    ((1024,), 5, 7, 0),                          # single-size group, eager
+    ((1024,), 3, 1, 16),                         # one trip: FIRST + LAST only
+    ((2048,), 2, 5, 2),
+    ((256, 2048), 4, 6, 3),                      # 256..2048 group
+    ((4096, 512), 2, 3, 1),                      # two workgroup sizes: two groups
+])
+def test_batch_is_bitwise_the_plain_path(sizes, count, trips, k):
+    cavs = mixed(count, sizes)
+    ref, ref_tr = plain_reference(cavs, trips)
+    plans, Es, Ns = make(cavs)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_set_graph_trips(b, k)
+    lsr.lsr_batch_roundtrips(b, Es, Ns, trips)
+    for p in plans:
+        p.sync()
+    for i, (p, e, n) in enumerate(zip(plans, Es, Ns)):
+        assert torch.equal(e, ref[i][0]), "cavity %d (N=%d) field" % (i, cavs[i].N)
+        assert torch.equal(n, ref[i][1]), "cavity %d (N=%d) inversion" % (i, cavs[i].N)
+        assert np.array_equal(p.trace(trips), ref_tr[i])
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
+
+
+def test_batch_graph_replays_and_repeated_calls_match_eager():
+    cavs = mixed(6, (512, 1024))
+    plans, Es, Ns = make(cavs)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_set_graph_trips(b, 3)
+    for _ in range(3):          # graph replayed several times across calls
+        lsr.lsr_batch_roundtrips(b, Es, Ns, 7)
+        torch.cuda.synchronize()
+    ref, _ = plain_reference(cavs, 21)
+    for i in range(len(cavs)):
+        assert torch.equal(Es[i], ref[i][0]) and torch.equal(Ns[i], ref[i][1])
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
+
+
+def test_batch_fifty_trips_against_oracle():
+    cavs = mixed(4, (256, 384, 512, 768))
+    plans, Es, Ns = make(cavs)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_roundtrips(b, Es, Ns, 50)
+    for p in plans:
+        p.sync()
+    for c, e, n in zip(cavs, Es, Ns):
+        eo, no, _ = oracle.run(oracle_params(c), *initial_state(c), 50)
+        assert rel(e.cpu().numpy(), eo) <= 1e-5 and rel(n.cpu().numpy(), no) <= 1e-5
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
+
+
+def test_batch_diag_and_bad_arguments():
+    cavs = mixed(2, (256,))
+    plans, Es, Ns = make(cavs)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    d = lsr.lsr_batch_diag(b, 1, Es[1], Ns[1], lsr.lsr_plan_nbins(plans[1].handle))
+    assert d["energy"] > 0
+    with pytest.raises(lsr.LsrError):
+        lsr.lsr_batch_roundtrips(b, Es, Ns, -2)
+    with pytest.raises(lsr.LsrError):
+        lsr.lsr_batch_diag(b, 5, Es[0], Ns[0], 10)
+    with pytest.raises(lsr.LsrError) as ei:
+        lsr.lsr_batch_create([plans[0].handle, plans[0].handle])
+    assert ei.value.code == lsr.LSR_EINVAL
+    f64 = lsr.Plan(cavs[0], prec=lsr.LSR_PREC_FP64)
+    with pytest.raises(lsr.LsrError) as ei:
+        lsr.lsr_batch_create([f64.handle])
+    assert ei.value.code == lsr.LSR_EUNSUPPORTED
+    lsr.lsr_batch_destroy(b)
+    for p in plans + [f64]:
+        p.close()
+
+
+def test_autotune_writes_cache_and_keeps_results(tmp_path):
+    cavs = mixed(3, (512,))
+    plans, Es, Ns = make(cavs)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    path = str(tmp_path / "tune.json")
+    lsr.lsr_autotune(None, b, path)
+    text = open(path).read()
+    assert "gfx950:batch:512x3;" in text
+    lsr.lsr_batch_roundtrips(b, Es, Ns, 9)
+    ref, _ = plain_reference(cavs, 9)
+    for i in range(len(cavs)):
+        assert torch.equal(Es[i], ref[i][0]) and torch.equal(Ns[i], ref[i][1])
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
