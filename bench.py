@@ -5,11 +5,12 @@ A step is one round trip of every cavity of the workload.  The workload is a
 set of 1024^2 cavities whose Fresnel number, pump ratio, T1 and R follow the
 batched sweep's parameter draws (F log-uniform in [100, 1000], pump U[1.2, 4],
 T1 U[200, 5000], R U[0.8, 0.98]; seeded noise fields, sigma = 1e-3), in the
-FP64-table precision form.  "batched" advances all cavities together
-(persistent kernel per round trip, replayed as a HIP graph); "plain" launches
-the row and column kernels of each cavity separately.
+FP64-table precision form (FP32 field).  "batched" advances all cavities
+together (grouped row/column pass launches or a persistent kernel per round
+trip, replayed as HIP graphs, launch shape from the autotune cache);
+"plain" launches the row and column kernels of each cavity separately.
 
-Prints one JSON line (rank 0).  Inputs are resident in HBM before timing.
+Prints one JSON line.  Inputs are resident in HBM before timing.
 """
 from __future__ import annotations
 
@@ -17,7 +18,6 @@ import argparse
 import glob
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -26,9 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-ROW_BYTES_PER_PT = 24          # row pass: field R+W 16 B, inversion R+W 8 B
-COL_BYTES_PER_PT = 16          # column pass: field R+W
+ROW_BYTES_PER_PT = 24          # row pass: field read+write 16 B, inversion read+write 8 B
+COL_BYTES_PER_PT = 16          # column pass: field read+write 16 B
 TRIP_BYTES_PER_PT = ROW_BYTES_PER_PT + COL_BYTES_PER_PT
+TUNE_CACHE = os.path.join(ROOT, "paper_1410_2855_amd", "tune_cache.json")
 
 
 def kernel_source_hash() -> str:
@@ -40,8 +41,9 @@ def kernel_source_hash() -> str:
 
 
 def load_traffic(kernel: str, pts_per_launch: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources; else None."""
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel
+    calibration) from the committed rocprofv3 summary, if it was taken on the
+    current kernel sources and workload; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -53,15 +55,12 @@ def load_traffic(kernel: str, pts_per_launch: int):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(seconds_target: float = 12.0):
-    """The FP64 oracle, single-threaded, on the first cavity of the workload:
-    as many 1024^2 round trips as fit in about seconds_target."""
-    import numpy as np
-
+def cpu_baseline(cav, seconds_target: float = 12.0):
+    """The FP64 oracle, single-threaded, on one 1024^2 cavity of the workload:
+    as many round trips as fit in about seconds_target."""
     import oracle
-    from paper_1410_2855_amd.inputs import initial_state, oracle_params, sweep_1024
+    from paper_1410_2855_amd.inputs import initial_state, oracle_params
 
-    cav = sweep_1024(1)[0]
     e0, n0 = initial_state(cav)
     p = oracle_params(cav)
     t0 = time.perf_counter()
@@ -73,23 +72,27 @@ def cpu_baseline(seconds_target: float = 12.0):
     dt = time.perf_counter() - t0
     return {"value": cav.N * cav.N * trips / dt, "unit": "grid-pts*round-trips/s", "cores": 1,
             "kind": "oracle",
-            "sample": "%d round trips of one 1024^2 cavity of the workload, single-threaded FP64 C" % trips}
+            "sample": "%d round trips of one 1024^2 cavity of the workload (FP64 C, one thread)" % trips}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cavities", type=int, default=64)
-    ap.add_argument("--mode", choices=["auto", "plain", "batched"], default="auto")
+    ap.add_argument("--autotune", action="store_true", help="retune the batch and update the cache")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile", action="store_true", help="short run for a profiler: no baseline, no parity")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short batched run for a profiler, plus a copy kernel of known size")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the round-trip map of a cavity set is measured on a "
-              "single MI355X (cavities are independent; see the design notes for sharding)", file=sys.stderr)
+        print("bench.py measures one GPU only: every cavity of the workload is independent and the "
+              "whole set runs on a single MI355X; sharding across GPUs is a design note, not a run",
+              file=sys.stderr)
         sys.exit(2)
+    os.environ.setdefault("LSR_TUNE_CACHE", TUNE_CACHE)
 
     import numpy as np
     import torch
@@ -105,34 +108,23 @@ def main():
     plans, Es, Ns = [], [], []
     for c in cavs:
         p = lsr.Plan(c, prec=lsr.LSR_PREC_FP64TAB, stream=stream)
-        e0, n0 = initial_state(c)
-        e, n = p.state(e0, n0, device=dev)
+        e, n = p.state(*initial_state(c), device=dev)
         plans.append(p)
         Es.append(e)
         Ns.append(n)
     torch.cuda.synchronize()
     pts = sum(c.N * c.N for c in cavs)
+    batch = lsr.lsr_batch_create([p.handle for p in plans])
+    if args.autotune:
+        lsr.lsr_autotune(None, batch, TUNE_CACHE)
+    cfg = lsr.lsr_batch_configure(batch)
+
+    def run_batched(k):
+        lsr.lsr_batch_roundtrips(batch, Es, Ns, k)
 
     def run_plain(k):
         for p, e, n in zip(plans, Es, Ns):
             p.roundtrips(e, n, k)
-
-    batch = None
-    mode = args.mode
-    if mode in ("auto", "batched"):
-        try:
-            batch = lsr.lsr_batch_create([p.handle for p in plans])
-        except lsr.LsrError:
-            if mode == "batched":
-                raise
-            batch = None
-    if batch is None:
-        mode = "plain"
-    else:
-        mode = "batched"
-
-    def run_batched(k):
-        lsr.lsr_batch_roundtrips(batch, Es, Ns, k)
 
     def timed(fn, steps, warmup):
         fn(warmup)
@@ -142,38 +134,37 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    # plain path: always measured (it is the comparison)
-    plain_warm = max(1, args.warmup // 4) if mode == "batched" else args.warmup
-    plain_steps = max(1, args.steps // 4) if mode == "batched" else args.steps
-    t_plain = timed(run_plain, plain_steps, plain_warm)
+    if args.profile:
+        # calibration copy of known size for the traffic counters: 256 MiB
+        x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        t = timed(run_batched, args.steps, args.warmup)
+        print(json.dumps({"profile": True, "ms_per_step": t * 1e3, "config": cfg,
+                          "copy_bytes_each_way": x.numel() * 4}), flush=True)
+        return
+
+    t_step = timed(run_batched, args.steps, args.warmup)
+    value = pts / t_step
+    t_plain = timed(run_plain, max(1, args.steps // 4), max(1, args.warmup // 4))
     plain_value = pts / t_plain
-    result_mode = "plain"
-    t_step, value = t_plain, plain_value
-    if mode == "batched":
-        t_step = timed(run_batched, args.steps, args.warmup)
-        value = pts / t_step
-        result_mode = "batched"
 
-    for p in plans:
-        p.sync()
-
-    # dominant kernel: live HIP-event timing on the plan's stream
-    e, n = Es[0], Ns[0]
-    row_ms, col_ms = lsr.lsr_time_kernels(plans[0].handle, e, n, 20)
-    n2 = cavs[0].N * cavs[0].N
-    kernels = {
-        "row_pass": (row_ms, ROW_BYTES_PER_PT * n2, n2),
-        "column_pass": (col_ms, COL_BYTES_PER_PT * n2, n2),
-    }
+    # dominant kernel: live HIP-event timing on the batch's stream
+    row_ms, col_ms, trip_ms = lsr.lsr_batch_time_kernels(batch, Es, Ns, 12)
+    if cfg["engine"] == 1:
+        kernels = {"row_pass": (row_ms, ROW_BYTES_PER_PT * pts), "column_pass": (col_ms, COL_BYTES_PER_PT * pts)}
+    else:
+        kernels = {"round_trip": (row_ms, TRIP_BYTES_PER_PT * pts)}
     dom = max(kernels, key=lambda k: kernels[k][0])
-    ms, nbytes, npts = kernels[dom]
+    ms, nbytes = kernels[dom]
     achieved = nbytes / (ms * 1e-3) / 1e9
-    traffic = load_traffic(dom, npts)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom, "launch_ms": round(ms, 5),
-                "algorithmic_bytes_per_launch": nbytes,
-                "other_kernels_ms": {k: round(v[0], 5) for k, v in kernels.items() if k != dom}}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, pts),
+                "kernel": dom, "launch_ms": round(ms, 5), "algorithmic_bytes_per_launch": nbytes,
+                "bytes_per_point": nbytes // pts,
+                "other_kernels_ms": {k: round(v[0], 5) for k, v in kernels.items() if k != dom},
+                "event_trip_ms": round(trip_ms, 5)}
 
     out = {
         "metric": "grid-pts x round-trips/s at 1024^2 (batched vs plain)",
@@ -188,19 +179,37 @@ def main():
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": "%d cavities at 1024^2, sweep parameter draws, FP64-table form" % len(cavs),
-                   "grid": 1024, "cavities": len(cavs), "mode": result_mode,
-                   "precision": "fp32 field, fp64-built tables"},
+        "config": {"workload": "%d cavities at 1024^2 (sweep parameter draws), FP64-table form" % len(cavs),
+                   "grid": 1024, "cavities": len(cavs), "mode": "batched",
+                   "engine": "grouped" if cfg["engine"] == 1 else "persistent", "launch": cfg},
         "plain": {"value": plain_value, "ms_per_step": t_plain * 1e3},
+        "speedup_batched_vs_plain": value / plain_value,
         "hbm_frac_whole_step": round(pts * TRIP_BYTES_PER_PT / t_step / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
     }
-    if batch is not None:
-        out["speedup_batched_vs_plain"] = value / plain_value
-    if not args.no_cpu_baseline and not args.profile:
-        out["cpu_baseline"] = cpu_baseline()
-    if batch is not None:
-        lsr.lsr_batch_destroy(batch)
+
+    if not args.no_parity:
+        # error vs the FP64 oracle after 50 batched round trips, cavity 0
+        import oracle
+        from paper_1410_2855_amd.inputs import oracle_params
+
+        for c, e, n in zip(cavs, Es, Ns):
+            e0, n0 = initial_state(c)
+            e.copy_(torch.from_numpy(e0).to(dev, torch.complex64))
+            n.copy_(torch.from_numpy(n0).to(dev, torch.float32))
+        run_batched(50)
+        torch.cuda.synchronize()
+        eo, no, _ = oracle.run(oracle_params(cavs[0]), *initial_state(cavs[0]), 50)
+        eg, ng = Es[0].cpu().numpy(), Ns[0].cpu().numpy()
+        out["err_vs_fp64"] = {"trips": 50, "cavity": 0,
+                              "rel_l2_E": float(np.linalg.norm(eg - eo) / np.linalg.norm(eo)),
+                              "rel_l2_N": float(np.linalg.norm(ng - no) / np.linalg.norm(no)),
+                              "tolerance": 1e-5}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cavs[0])
+    for p in plans:
+        p.sync()
+    lsr.lsr_batch_destroy(batch)
     for p in plans:
         p.close()
     print(json.dumps(out), flush=True)

@@ -166,7 +166,7 @@ void lsr_plan_destroy(lsr_plan p);
 /* ---------------------------------------------------------------------- */
 /* Batching: many cavities of uneven N and parameters advanced together by */
 /* one persistent kernel per round trip, replayed as a HIP graph of k      */
-/* round trips.  Only FP32 plans (PLAIN / FP64TAB) can be batched.         */
+/* round trips.  Only LSR_PREC_FP64TAB plans can be batched.              */
 /* ---------------------------------------------------------------------- */
 
 /* Build a batch over count >= 1 plans (borrowed).  The task table, the
@@ -198,6 +198,15 @@ int lsr_batch_set_graph_trips(lsr_batch b, int k);
  * (nullable) receives the resulting six values in this order. */
 int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, int chunk,
                         int lag, int graph_k, int* cfg_out);
+
+/* Profiling form of lsr_batch_roundtrips (eager, no graph): each launch is
+ * bracketed by HIP events on the batch's stream.  ms[0] = mean duration of
+ * the row-pass launch (all cavities' row blocks of one trip, middle trips
+ * only when n_trips > 1), ms[1] = mean column-pass launch, ms[2] = mean
+ * round trip (ms[0] + ms[1] + the gaps between them).  With the persistent
+ * engine the whole trip is one launch: ms[0] = ms[2], ms[1] = 0.
+ * Synchronises. */
+int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* Ninv, int n_trips, double* ms);
 
 void lsr_batch_destroy(lsr_batch b);
 

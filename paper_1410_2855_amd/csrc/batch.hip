@@ -368,7 +368,8 @@ int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count) {
     if (!plans || count < 1) return set_err(LSR_EINVAL, "a batch needs at least one plan");
     for (int i = 0; i < count; ++i) {
         if (!plans[i]) return set_err(LSR_EINVAL, "plan %d is NULL", i);
-        if (plans[i]->prec == PREC_FP64) return set_err(LSR_EUNSUPPORTED, "FP64 plans cannot be batched");
+        if (plans[i]->prec != PREC_FP64TAB)
+            return set_err(LSR_EUNSUPPORTED, "only FP64TAB plans (FP32 field, FP64-built tables) can be batched");
         if (plans[i]->device != plans[0]->device) return set_err(LSR_EINVAL, "plans on different devices");
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return set_err(LSR_EINVAL, "plan %d appears twice", i);
@@ -496,6 +497,73 @@ int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* N, int n_trip
     LSR_HIP(hipEventRecord(b->ev_out, b->stream));
     LSR_HIP(hipStreamWaitEvent(b->user, b->ev_out, 0));
     if (rc) return rc;
+    for (auto* p : b->plans) {
+        p->trips_done += (unsigned long long)n_trips;
+        p->last_n = n_trips;
+    }
+    return LSR_OK;
+}
+
+int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* N, int n_trips, double* ms) {
+    if (!b || !ms || !E || !N) return set_err(LSR_EINVAL, "bad arguments");
+    if (n_trips < 1) return set_err(LSR_EINVAL, "n_trips < 1");
+    DeviceGuard dg(b->device);
+    LSR_HIP(hipEventRecord(b->ev_in, b->user));
+    LSR_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    int rc = upload_descs(b, E, N, false);
+    if (rc) return rc;
+    // per trip: [e0] row [e1] col [e2]; trip t uses events 3t .. 3t+2
+    const int ne = 3 * (n_trips + 1);
+    std::vector<hipEvent_t> ev((size_t)ne, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& x : ev)
+                if (x) (void)hipEventDestroy(x);
+            return set_err(LSR_EDEVICE, "hipEventCreate failed");
+        }
+    const bool grouped = b->tune.engine == 1;
+    for (int t = 0; t <= n_trips && rc == LSR_OK; ++t) {
+        const int mode = t == 0 ? ROW_FIRST : (t == n_trips ? ROW_LAST : ROW_MID);
+        (void)hipEventRecord(ev[3 * t], b->stream);
+        if (grouped) {
+            for (auto& g : b->grp)
+                if (rc == LSR_OK && g.g->var[variant_of(b, g)].launch_pass(mode, TASK_ROW, b->stream, g.d_desc,
+                                                                          g.d_last, g.nlast))
+                    rc = set_err(LSR_EDEVICE, "row-pass launch failed");
+            (void)hipEventRecord(ev[3 * t + 1], b->stream);
+            if (mode != ROW_LAST)
+                for (auto& g : b->grp)
+                    if (rc == LSR_OK && g.g->var[variant_of(b, g)].launch_pass(mode, TASK_COL, b->stream,
+                                                                              g.d_desc, g.d_cols, g.ncols))
+                        rc = set_err(LSR_EDEVICE, "column-pass launch failed");
+        } else {
+            rc = launch_trip(b, mode);
+            (void)hipEventRecord(ev[3 * t + 1], b->stream);
+        }
+        (void)hipEventRecord(ev[3 * t + 2], b->stream);
+    }
+    double row = 0, col = 0, trip = 0;
+    int nrow = 0;
+    if (rc == LSR_OK && hipEventSynchronize(ev[ne - 1]) == hipSuccess) {
+        for (int t = 0; t < n_trips; ++t) {
+            if (n_trips > 1 && t == 0) continue;   // the FIRST form differs
+            float a = 0, c = 0, w = 0;
+            (void)hipEventElapsedTime(&a, ev[3 * t], ev[3 * t + 1]);
+            (void)hipEventElapsedTime(&c, ev[3 * t + 1], ev[3 * t + 2]);
+            (void)hipEventElapsedTime(&w, ev[3 * t], ev[3 * t + 3]);
+            row += a;
+            col += c;
+            trip += w;
+            ++nrow;
+        }
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    LSR_HIP(hipEventRecord(b->ev_out, b->stream));
+    LSR_HIP(hipStreamWaitEvent(b->user, b->ev_out, 0));
+    if (rc) return rc;
+    ms[0] = nrow ? row / nrow : 0;
+    ms[1] = grouped && nrow ? col / nrow : 0;
+    ms[2] = nrow ? trip / nrow : 0;
     for (auto* p : b->plans) {
         p->trips_done += (unsigned long long)n_trips;
         p->last_n = n_trips;

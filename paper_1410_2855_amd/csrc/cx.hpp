@@ -38,6 +38,26 @@ __device__ __forceinline__ cx<T> rot_q(cx<T> a) {
     else return {a.im, -a.re};
 }
 
+// Global memory access at a 32-bit byte offset from a uniform base.  The
+// pointers of a cavity reach the kernels inside a descriptor, so the compiler
+// cannot tell they address global memory and would emit flat accesses with a
+// 64-bit address each; the cast to the global address space and the 32-bit
+// offset let it use global_load/store with a scalar base and a 32-bit vector
+// offset.  A cavity's arrays are far below 4 GiB.
+#define LSR_GLOBAL __attribute__((address_space(1)))
+// CST is a compile-time byte offset applied on the pointer side, so it folds
+// into the instruction's immediate offset.
+template <typename V, int CST = 0>
+__device__ __forceinline__ V gld(const void* base, unsigned byte_off) {
+    const LSR_GLOBAL char* b = (const LSR_GLOBAL char*)base + CST;
+    return *(const LSR_GLOBAL V*)(b + byte_off);
+}
+template <typename V, int CST = 0>
+__device__ __forceinline__ void gst(void* base, unsigned byte_off, const V& v) {
+    LSR_GLOBAL char* b = (LSR_GLOBAL char*)base + CST;
+    *(LSR_GLOBAL V*)(b + byte_off) = v;
+}
+
 // Compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).
 template <int B, int E, class F>
 __device__ __forceinline__ void sfor(F&& f) {

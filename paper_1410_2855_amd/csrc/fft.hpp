@@ -119,19 +119,24 @@ __device__ __forceinline__ void line_sync() {
     }
 }
 
-// Load R consecutive twiddles (16-byte vector loads; R even or R == 3).
-template <int R, typename T>
-__device__ __forceinline__ void load_tw(cx<T>* w, const cx<T>* __restrict__ src) {
-    if constexpr (sizeof(cx<T>) == 8 && (R % 2 == 0)) {
-        const float4* s4 = reinterpret_cast<const float4*>(src);
+// Load the R twiddles of sub-transform k of a pass whose table segment
+// starts at entry SEG (16-byte vector loads; R even or R == 3).
+template <int R, int SEG, typename T>
+__device__ __forceinline__ void load_tw(cx<T>* w, const cx<T>* __restrict__ tw, int k) {
+    constexpr int E = (int)sizeof(cx<T>);
+    const unsigned off = (unsigned)k * (unsigned)(R * E);
+    if constexpr (E == 8 && (R % 2 == 0)) {
         sfor<0, R / 2>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            float4 q = s4[i];
+            const float4 q = gld<float4, SEG * E + 16 * i>(tw, off);
             w[2 * i] = {(T)q.x, (T)q.y};
             w[2 * i + 1] = {(T)q.z, (T)q.w};
         });
     } else {
-        sfor<0, R>([&](auto ic) { w[decltype(ic)::value] = src[decltype(ic)::value]; });
+        sfor<0, R>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            w[i] = gld<cx<T>, SEG * E + E * i>(tw, off);
+        });
     }
 }
 
@@ -148,7 +153,7 @@ __device__ __forceinline__ void pass_compute(cx<T>* v, int lane, const cx<T>* __
             const int j = lane + b * S::L;
             const int k = j % Ns;
             cx<T> w[R];
-            load_tw<R>(w, tw + S::tw_off(DIR, PASS) + k * R);
+            load_tw<R, S::tw_off(DIR, PASS)>(w, tw, k);
             sfor<1, R>([&](auto rc) {
                 constexpr int r = decltype(rc)::value;
                 x[r] = cmul(x[r], w[r]);
@@ -156,6 +161,25 @@ __device__ __forceinline__ void pass_compute(cx<T>* v, int lane, const cx<T>* __
         }
         dft<R, DIR>(x);
     });
+}
+
+// LDS slot of line position base + r*stride, r < R.  The padding is linear
+// in r -- pad(base + r s) = pad(base) + r s + (r s)/16 -- whenever no two
+// terms of the walk straddle a 16-block boundary differently: for strides
+// that are multiples of 16, and for the Stockham scatter when s divides 16
+// and s*R divides or is a multiple of 16 (base mod 16 < s there, or the whole
+// walk stays inside one block).  Then every slot is the base slot plus a
+// compile-time offset, an immediate of the LDS instruction.
+template <int STRIDE, int R>
+constexpr bool linear_walk() {
+    return STRIDE % 16 == 0 ||
+           (16 % STRIDE == 0 && ((STRIDE * R) % 16 == 0 || 16 % (STRIDE * R) == 0));
+}
+
+template <class S, int STRIDE, int R>
+__device__ __forceinline__ int slot(int padded_base, int base, int r) {
+    if constexpr (linear_walk<STRIDE, R>()) return padded_base + r * STRIDE + ((r * STRIDE) >> 4);
+    else return S::pad(base + r * STRIDE);
 }
 
 // Write the outputs of pass PASS to their Stockham positions in the line.
@@ -169,9 +193,10 @@ __device__ __forceinline__ void pass_scatter(const cx<T>* v, cx<T>* line, int la
         const int j = lane + b * S::L;
         const int k = j % Ns;
         const int base = (j / Ns) * Ns * R + k;
+        const int pb = S::pad(base);
         sfor<0, R>([&](auto rc) {
             constexpr int r = decltype(rc)::value;
-            line[S::pad(base + r * Ns)] = v[b * R + r];
+            line[slot<S, Ns, R>(pb, base, r)] = v[b * R + r];
         });
     });
 }
@@ -183,9 +208,10 @@ __device__ __forceinline__ void gather_in(cx<T>* v, const cx<T>* line, int lane)
     sfor<0, B>([&](auto bc) {
         constexpr int b = decltype(bc)::value;
         const int j = lane + b * S::L;
+        const int pb = S::pad(j);
         sfor<0, R>([&](auto rc) {
             constexpr int r = decltype(rc)::value;
-            v[b * R + r] = line[S::pad(j + r * (S::N / R))];
+            v[b * R + r] = line[slot<S, S::N / R, R>(pb, j, r)];
         });
     });
 }
@@ -197,9 +223,10 @@ __device__ __forceinline__ void scatter_out(const cx<T>* v, cx<T>* line, int lan
     sfor<0, B>([&](auto bc) {
         constexpr int b = decltype(bc)::value;
         const int j = lane + b * S::L;
+        const int pb = S::pad(j);
         sfor<0, R>([&](auto rc) {
             constexpr int r = decltype(rc)::value;
-            line[S::pad(j + r * (S::N / R))] = v[b * R + r];
+            line[slot<S, S::N / R, R>(pb, j, r)] = v[b * R + r];
         });
     });
 }

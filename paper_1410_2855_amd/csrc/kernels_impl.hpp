@@ -14,7 +14,7 @@ __global__ __launch_bounds__(S::THREADS) void k_row(CavDesc d) {
     row_task<S, T, MODE>(d, blockIdx.x, lds, red);
 }
 
-template <class S, typename T, int MODE>
+template <class S, typename T, int MODE, int PROP>
 __global__ __launch_bounds__(S::THREADS) void k_col(CavDesc d) {
     __shared__ cx<T> lds[S::LDS_ELEMS];
     if constexpr (MODE == COL_PROP) {
@@ -22,7 +22,7 @@ __global__ __launch_bounds__(S::THREADS) void k_col(CavDesc d) {
         // per-block sums into the trace ring
         if (blockIdx.x == 0 && threadIdx.x < 64) finalize_sums(d);
     }
-    col_task<S, T, MODE>(d, blockIdx.x, lds);
+    col_task<S, T, MODE, PROP>(d, blockIdx.x, lds);
 }
 
 template <class S, typename T>
@@ -42,8 +42,11 @@ template <class S, typename T>
 int launch_col_t(const CavDesc& d, int mode, hipStream_t st) {
     const dim3 g(S::N / S::LPW), b(S::THREADS);
     switch (mode) {
-    case COL_PROP: hipLaunchKernelGGL((k_col<S, T, COL_PROP>), g, b, 0, st, d); break;
-    case COL_DIAG: hipLaunchKernelGGL((k_col<S, T, COL_DIAG>), g, b, 0, st, d); break;
+    case COL_PROP:
+        if (d.prec == PREC_PLAIN) hipLaunchKernelGGL((k_col<S, T, COL_PROP, PROP_PHASE>), g, b, 0, st, d);
+        else hipLaunchKernelGGL((k_col<S, T, COL_PROP, PROP_TABLE>), g, b, 0, st, d);
+        break;
+    case COL_DIAG: hipLaunchKernelGGL((k_col<S, T, COL_DIAG, PROP_TABLE>), g, b, 0, st, d); break;
     default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -3;

@@ -48,7 +48,10 @@ __device__ __forceinline__ typename V16<T>::type pack16(const cx<T>* e) {
     else return double2{e[0].re, e[0].im};
 }
 
-__device__ __forceinline__ float ex(float x) { return expf(x); }
+// exp(x) as 2^(x log2 e): one v_exp_f32 (1-ulp hardware 2^x) for FP32, the
+// library exp for FP64.  The FP32 form feeds only the gain and aperture
+// factors, whose arguments are O(1) where the factors matter.
+__device__ __forceinline__ float ex(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896340736f); }
 __device__ __forceinline__ double ex(double x) { return exp(x); }
 __device__ __forceinline__ void sc(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sc(double x, double* s, double* c) { sincos(x, s, c); }
@@ -95,9 +98,11 @@ __device__ __forceinline__ void stage_in_rows(const cx<T>* __restrict__ blk, cx<
     constexpr int NCH = S::LPW * S::N / EPC<T>;
     static_assert(NCH % S::THREADS == 0, "row staging must tile the workgroup");
     constexpr int IT = NCH / S::THREADS;
-    const V* src = reinterpret_cast<const V*>(blk);
     V q[IT];
-    sfor<0, IT>([&](auto ic) { q[decltype(ic)::value] = src[tid + decltype(ic)::value * S::THREADS]; });
+    sfor<0, IT>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        q[i] = gld<V, 16 * i * S::THREADS>(blk, 16u * (unsigned)tid);
+    });
     sfor<0, IT>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         int l, x;
@@ -113,7 +118,6 @@ __device__ __forceinline__ void stage_out_rows(cx<T>* __restrict__ blk, const cx
     using V = typename V16<T>::type;
     constexpr int NCH = S::LPW * S::N / EPC<T>;
     constexpr int IT = NCH / S::THREADS;
-    V* dst = reinterpret_cast<V*>(blk);
     sfor<0, IT>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         const int c = tid + i * S::THREADS;
@@ -121,20 +125,22 @@ __device__ __forceinline__ void stage_out_rows(cx<T>* __restrict__ blk, const cx
         row_chunk_pos<S, T, LAYOUT>(c, l, x);
         cx<T> e[EPC<T>];
         sfor<0, EPC<T>>([&](auto kc) { e[decltype(kc)::value] = lds[l * S::LINE + S::pad(x + decltype(kc)::value)]; });
-        dst[c] = pack16<T>(e);
+        gst<V, 16 * i * S::THREADS>(blk, 16u * (unsigned)tid, pack16<T>(e));
     });
 }
 
 // Column block cb of the tiled layout: tiles (i, cb), i = 0..N/LPW-1.
+// Returns the chunk index relative to the block's first tile (32 bits: a
+// cavity's field is below 4 GiB).
 template <class S, typename T>
-__device__ __forceinline__ size_t col_chunk(int c, int cb, int& line, int& y) {
+__device__ __forceinline__ unsigned col_chunk(int c, int& line, int& y) {
     constexpr int TT = S::LPW * S::LPW;
     constexpr int CPT = TT / EPC<T>;
     const int i = c / CPT;
     const int o = (c % CPT) * EPC<T>;
     line = o % S::LPW;
     y = i * S::LPW + o / S::LPW;
-    return ((size_t)i * S::LPW * S::N + (size_t)cb * TT + o) / EPC<T>;
+    return (unsigned)(i * S::LPW * S::N + o) / EPC<T>;
 }
 
 template <class S, typename T>
@@ -144,15 +150,15 @@ __device__ __forceinline__ void stage_in_cols(const cx<T>* __restrict__ E, int c
     constexpr int NCH = S::N * S::LPW / EPC<T>;
     static_assert(NCH % S::THREADS == 0, "column staging must tile the workgroup");
     constexpr int IT = NCH / S::THREADS;
-    const V* src = reinterpret_cast<const V*>(E);
+    const cx<T>* src = E + (size_t)cb * S::LPW * S::LPW;
     V q[IT];
-    size_t off[IT];
+    unsigned off[IT];
     int ln[IT], yy[IT];
     sfor<0, IT>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        off[i] = col_chunk<S, T>(tid + i * S::THREADS, cb, ln[i], yy[i]);
+        off[i] = col_chunk<S, T>(tid + i * S::THREADS, ln[i], yy[i]);
     });
-    sfor<0, IT>([&](auto ic) { q[decltype(ic)::value] = src[off[decltype(ic)::value]]; });
+    sfor<0, IT>([&](auto ic) { q[decltype(ic)::value] = gld<V>(src, 16u * off[decltype(ic)::value]); });
     sfor<0, IT>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         cx<T> e[EPC<T>];
@@ -169,17 +175,17 @@ __device__ __forceinline__ void stage_out_cols(cx<T>* __restrict__ E, int cb, co
     using V = typename V16<T>::type;
     constexpr int NCH = S::N * S::LPW / EPC<T>;
     constexpr int IT = NCH / S::THREADS;
-    V* dst = reinterpret_cast<V*>(E);
+    cx<T>* dst = E + (size_t)cb * S::LPW * S::LPW;
     sfor<0, IT>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         int line, y;
-        const size_t off = col_chunk<S, T>(tid + i * S::THREADS, cb, line, y);
+        const unsigned off = col_chunk<S, T>(tid + i * S::THREADS, line, y);
         cx<T> e[EPC<T>];
         sfor<0, EPC<T>>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
             e[k] = lds[(line + k) * S::LINE + S::pad(y)];
         });
-        dst[off] = pack16<T>(e);
+        gst<V>(dst, 16u * off, pack16<T>(e));
     });
 }
 
@@ -233,57 +239,76 @@ __device__ __forceinline__ void finalize_sums(const CavDesc& d) {
 
 // ---------------------------------------------------------------------------
 // Local step, inversion update and diagnostics sums on the lane's points of
-// row y (register order of the first forward radix = natural x order).
+// row y (register order of the first forward radix = natural x order).  Done
+// in phases over all P points so the aperture power runs as one uniform loop.
 template <class S, typename T, int MODE>
 __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc& d, int y, int lane,
-                                           double* acc) {
+                                           T* acc) {
     constexpr int R = R_FIRST<S>;
     constexpr int B = S::P / R;
+    constexpr int P = S::P;
     const T dx = (T)d.dx;
     const T half = (T)(0.5 * S::N);
     const T Y = ((T)y - half) * dx;
     const T Y2 = Y * Y;
     const T sqR = (T)d.sqrtR, N0 = (T)d.N0, iT1 = (T)d.inv_T1, mamp = (T)d.mod_amp;
     const T ir = (T)d.inv_r0sq;
-    const int kind = d.ap_kind, hord = d.ap_half_order;
+    const int kind = d.ap_kind;
     const T* pc = static_cast<const T*>(d.pump_c);
     const cx<T>* foc = static_cast<const cx<T>*>(d.foc);
-    const T* mask = static_cast<const T*>(d.mask);
-    T* ninv = static_cast<T*>(d.Ninv);
+    // byte offsets of row y from the cavity's (uniform) array bases
+    const unsigned row = (unsigned)y * (unsigned)S::N * (unsigned)sizeof(T);
+
+    // aperture amplitude A(x, y)
+    T A[P];
+    if (kind == AP_MASK) {
+        sfor<0, P>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            A[i] = gld<T>(d.mask, row + (unsigned)sizeof(T) * (unsigned)reg_pos<S, R>(lane, i / R, i % R));
+        });
+    } else if (kind == AP_NONE) {
+        sfor<0, P>([&](auto ic) { A[decltype(ic)::value] = (T)1; });
+    } else {
+        // u = r^2/r0^2 (super-Gaussian) or r^2/(2 r0^2) (Gaussian); exponent
+        // u^h, h = order/2, by squaring (uniform loop)
+        T u[P];
+        sfor<0, P>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const T X = ((T)reg_pos<S, R>(lane, i / R, i % R) - half) * dx;
+            u[i] = fma_(X, X, Y2) * ir;
+            A[i] = (T)1;
+        });
+        for (int e = kind == AP_SUPERGAUSS ? d.ap_half_order : 1; e; e >>= 1) {
+            if (e & 1) sfor<0, P>([&](auto ic) { A[decltype(ic)::value] *= u[decltype(ic)::value]; });
+            sfor<0, P>([&](auto ic) { u[decltype(ic)::value] *= u[decltype(ic)::value]; });
+        }
+        sfor<0, P>([&](auto ic) { A[decltype(ic)::value] = ex(-A[decltype(ic)::value]); });
+    }
     const T pcy = pc ? pc[y] : (T)0;
     const cx<T> fy = foc ? foc[y] : cx<T>{(T)1, (T)0};
     sfor<0, B>([&](auto bc) {
         constexpr int b = decltype(bc)::value;
         sfor<0, R>([&](auto rc) {
             constexpr int r = decltype(rc)::value;
-            const int x = reg_pos<S, R>(lane, b, r);
-            const cx<T> e = v[b * R + r];
-            const T n = nv[b * R + r];
+            constexpr int i = b * R + r;
+            const unsigned x = (unsigned)reg_pos<S, R>(lane, b, r);
+            const cx<T> e = v[i];
+            const T n = nv[i];
             const T I = fma_(e.re, e.re, e.im * e.im);
-            T A = (T)1;
-            if (kind == AP_MASK) {
-                A = mask[(size_t)y * S::N + x];
-            } else if (kind != AP_NONE) {
-                const T X = ((T)x - half) * dx;
-                const T u = (X * X + Y2) * ir;
-                T p = u;
-                if (kind == AP_SUPERGAUSS)
-                    for (int k = 1; k < hord; ++k) p *= u;
-                A = ex(-p);
-            }
             const T eh = ex((T)0.5 * n);          // frozen-inversion amplitude gain
-            const T A2 = A * A;
-            const T aeh = A * eh;
-            acc[0] += (double)I;
-            acc[1] += (double)(A2 * I);
-            acc[2] += (double)(aeh * aeh * I);
-            acc[3] += (double)n;
+            const T A2 = A[i] * A[i];
+            const T aeh = A[i] * eh;
+            acc[0] += I;
+            acc[1] = fma_(A2, I, acc[1]);
+            acc[2] = fma_(aeh * aeh, I, acc[2]);
+            acc[3] += n;
             cx<T> g = scale(e, sqR * aeh);
-            if (foc) g = cmul(g, cmul(foc[x], fy));
-            v[b * R + r] = g;
+            if (foc) g = cmul(g, cmul(gld<cx<T>>(foc, (unsigned)sizeof(cx<T>) * x), fy));
+            v[i] = g;
             if constexpr (MODE != ROW_DIAG) {
-                const T pump = pc ? N0 * fma_(mamp * pc[x], pcy, (T)1) : N0;
-                ninv[(size_t)y * S::N + x] = fma_(-n, I, fma_(pump - n, iT1, n));
+                const T pump = pc ? N0 * fma_(mamp * gld<T>(pc, (unsigned)sizeof(T) * x), pcy, (T)1) : N0;
+                gst<T, (int)sizeof(T) * (b * S::L + r * (S::N / R))>(
+                    d.Ninv, row + (unsigned)sizeof(T) * (unsigned)lane, fma_(-n, I, fma_(pump - n, iT1, n)));
             }
         });
     });
@@ -303,11 +328,12 @@ __device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, d
 
     T nv[S::P];
     if constexpr (MODE != ROW_LAST) {
-        const T* ninv = static_cast<const T*>(d.Ninv) + (size_t)y * S::N;
+        const unsigned row = (unsigned)y * (unsigned)S::N * (unsigned)sizeof(T);
         sfor<0, S::P / RF>([&](auto bc) {
             sfor<0, RF>([&](auto rc) {
                 constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
-                nv[b * RF + r] = ninv[reg_pos<S, RF>(lane, b, r)];
+                nv[b * RF + r] = gld<T, (int)sizeof(T) * (b * S::L + r * (S::N / RF))>(
+                    d.Ninv, row + (unsigned)sizeof(T) * (unsigned)lane);
             });
         });
     }
@@ -330,9 +356,12 @@ __device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, d
         stage_out_rows<S, T, 0>(blk, lds, tid);
         return;
     } else {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        // per-lane sums in the field's precision (P terms), FP64 from the
+        // wave reduction on
+        T acc[4] = {(T)0, (T)0, (T)0, (T)0};
         local_step<S, T, MODE>(v, nv, d, y, lane, acc);
-        block_sums_store<S>(acc, red, d.partials + 4 * rb, tid);
+        double accd[4] = {(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
+        block_sums_store<S>(accd, red, d.partials + 4 * rb, tid);
         fft_line<S, FWD>(v, myl, lane, tw);
         scatter_out<S, RL>(v, myl, lane);
         __syncthreads();
@@ -342,7 +371,12 @@ __device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, d
     }
 }
 
-template <class S, typename T, int MODE>
+// PROP: propagator form of the column pass -- PROP_TABLE multiplies by the
+// FP64-built separable table hx(p) hx(q); PROP_PHASE evaluates the phase
+// pi lambda L (fx^2 + fy^2) in the field's precision (the plain form).
+enum : int { PROP_TABLE = 0, PROP_PHASE = 1 };
+
+template <class S, typename T, int MODE, int PROP = PROP_TABLE>
 __device__ __forceinline__ void col_task(const CavDesc& d, int cb, cx<T>* lds) {
     const int tid = opaque_tid();
     const int line = tid / S::L, lane = tid % S::L;
@@ -380,7 +414,7 @@ __device__ __forceinline__ void col_task(const CavDesc& d, int cb, cx<T>* lds) {
         return;
     } else {
         // propagator H(kx, ky) = exp(-i pi lambda L (fx^2 + fy^2)) / N^2
-        if (d.prec == PREC_PLAIN) {
+        if constexpr (PROP == PROP_PHASE) {
             const T c = (T)d.phase_c, inn = (T)d.inv_nn;
             const int px2 = px * px;
             sfor<0, B>([&](auto bc) {
@@ -394,11 +428,11 @@ __device__ __forceinline__ void col_task(const CavDesc& d, int cb, cx<T>* lds) {
             });
         } else {
             const cx<T>* hx = static_cast<const cx<T>*>(d.hx);
-            const cx<T> hk = hx[kx];
+            const cx<T> hk = gld<cx<T>>(hx, (unsigned)sizeof(cx<T>) * (unsigned)kx);
             sfor<0, B>([&](auto bc) {
                 sfor<0, RL>([&](auto rc) {
                     constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
-                    const cx<T> h = cmul(hk, hx[reg_pos<S, RL>(lane, b, r)]);
+                    const cx<T> h = cmul(hk, gld<cx<T>>(hx, (unsigned)sizeof(cx<T>) * (unsigned)reg_pos<S, RL>(lane, b, r)));
                     v[b * RL + r] = cmul(v[b * RL + r], h);
                 });
             });

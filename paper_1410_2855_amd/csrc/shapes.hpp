@@ -62,9 +62,11 @@ struct Shape {
     static constexpr int TW_TOTAL = tw_off(INV, NP);
 
     // LDS: one padded line per handled line; one spare element per 16 keeps
-    // the Stockham scatter of small sub-lengths free of bank conflicts.
+    // the Stockham scatter of small sub-lengths free of bank conflicts, and a
+    // line stride of 4 (mod 16) elements puts the LPW lines a staging chunk
+    // row touches on different banks.
     static constexpr int pad(int i) { return i + (i >> 4); }
-    static constexpr int LINE = N_ + (N_ >> 4) + 2;
+    static constexpr int LINE = ((N_ + (N_ >> 4) + 15) / 16) * 16 + 4;
     static constexpr int LDS_ELEMS = LPW_ * LINE;
 
     static constexpr bool valid() {

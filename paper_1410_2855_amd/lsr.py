@@ -63,6 +63,7 @@ _SIGS = {
     "lsr_batch_diag": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(lsr_diag_out)]),
     "lsr_batch_set_graph_trips": (_i, [_vp, _i]),
     "lsr_batch_configure": (_i, [_vp, _i, _i, _i, _i, _i, _i, ctypes.POINTER(_i)]),
+    "lsr_batch_time_kernels": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, ctypes.POINTER(_d)]),
     "lsr_batch_destroy": (None, [_vp]),
     "lsr_autotune": (_i, [_vp, _vp, ctypes.c_char_p]),
     "lsr_last_error": (ctypes.c_char_p, []),
@@ -248,6 +249,15 @@ def lsr_batch_configure(batch, engine=-1, variant=-1, wgs_per_cu=-1, chunk=-1, l
     out = (ctypes.c_int * 6)()
     _check(load().lsr_batch_configure(batch, engine, variant, wgs_per_cu, chunk, lag, graph_k, out))
     return dict(zip(("engine", "variant", "wgs_per_cu", "chunk", "lag", "graph_k"), out[:]))
+
+
+def lsr_batch_time_kernels(batch, Es, Ns, n_trips: int):
+    """Mean (row-pass ms, column-pass ms, trip ms) over event-bracketed eager trips."""
+    e = (ctypes.c_void_p * len(Es))(*[_ptr(t) for t in Es])
+    n = (ctypes.c_void_p * len(Ns))(*[_ptr(t) for t in Ns])
+    ms = (ctypes.c_double * 3)()
+    _check(load().lsr_batch_time_kernels(batch, e, n, n_trips, ms))
+    return ms[0], ms[1], ms[2]
 
 
 def lsr_batch_destroy(batch):
