@@ -190,7 +190,10 @@ int lsr_batch_set_graph_trips(lsr_batch b, int k);
 /* Launch configuration of a batch; a negative argument keeps the current
  * value.  engine: 0 = one persistent kernel per round trip (task queue with
  * per-cavity row-to-column dependencies), 1 = one grouped launch per pass
- * (every cavity's row blocks, then every cavity's column blocks).  variant:
+ * (every cavity's row blocks, then every cavity's column blocks), 2 = grouped
+ * launches whose resident workgroups prefetch their next task's data while
+ * computing the current one (groups of a single grid size; other groups fall
+ * back to 1).  variant:
  * register-budget variant of the kernels (0 = 2 waves/SIMD, 1 = 3).
  * wgs_per_cu: resident workgroups per CU of the persistent kernel (0 =
  * occupancy limit).  chunk: tickets taken per queue access.  lag: packer lag

@@ -73,7 +73,8 @@ static void pack(const std::vector<int>& nrb, int lag, bool with_cols, std::vect
 static int default_lag() { return 2048; }
 
 struct Tune {
-    int engine = 1;       // 0 persistent kernel per trip, 1 grouped launch per pass
+    int engine = 1;       // 0 persistent kernel per trip, 1 grouped launch per pass,
+                          // 2 grouped and software-pipelined (single-size groups)
     int variant = 0;      // kernel variant (register budget) of each group
     int wgs_per_cu = 0;   // 0 = occupancy limit
     int chunk = 2;
@@ -163,6 +164,7 @@ struct BatchGroup {
     int ncols = 0;
     unsigned* d_ctrl = nullptr;
     int occ[4] = {1, 1, 1, 1};   // resident workgroups per CU of each variant
+    int occ_pipe[4][2] = {};     // same for the pipelined row / column pass
 };
 
 struct lsr_batch_s {
@@ -242,22 +244,31 @@ static int grid_of(const lsr_batch_s* b, const BatchGroup& g) {
     return per_cu * b->cus;
 }
 
+// One grouped pass (kind TASK_ROW or TASK_COL) of every group.
+static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind) {
+    for (auto& g : b->grp) {
+        const int v = variant_of(b, g);
+        const KernelVariant& kv = g.g->var[v];
+        const int4* tasks = kind == TASK_ROW ? g.d_last : g.d_cols;
+        const int nt = kind == TASK_ROW ? g.nlast : g.ncols;
+        int rc;
+        if (b->tune.engine == 2 && kv.launch_pipe)
+            rc = kv.launch_pipe(mode, kind, b->stream, g.d_desc, tasks, nt, g.occ_pipe[v][kind] * b->cus);
+        else
+            rc = kv.launch_pass(mode, kind, b->stream, g.d_desc, tasks, nt);
+        if (rc)
+            return set_err(LSR_EDEVICE, "%s-pass launch failed: %s", kind == TASK_ROW ? "row" : "column",
+                           hipGetErrorString(hipGetLastError()));
+    }
+    return LSR_OK;
+}
+
 static int launch_trip(lsr_batch_s* b, int mode) {
-    if (b->tune.engine == 1) {
+    if (b->tune.engine >= 1) {
         // grouped: every cavity's row blocks, then every cavity's column blocks
-        for (auto& g : b->grp) {
-            const KernelVariant& kv = g.g->var[variant_of(b, g)];
-            if (kv.launch_pass(mode, TASK_ROW, b->stream, g.d_desc, g.d_last, g.nlast))
-                return set_err(LSR_EDEVICE, "row-pass launch failed: %s", hipGetErrorString(hipGetLastError()));
-        }
-        if (mode != ROW_LAST)
-            for (auto& g : b->grp) {
-                const KernelVariant& kv = g.g->var[variant_of(b, g)];
-                if (kv.launch_pass(mode, TASK_COL, b->stream, g.d_desc, g.d_cols, g.ncols))
-                    return set_err(LSR_EDEVICE, "column-pass launch failed: %s",
-                                   hipGetErrorString(hipGetLastError()));
-            }
-        return LSR_OK;
+        int rc = launch_grouped_pass(b, mode, TASK_ROW);
+        if (rc == LSR_OK && mode != ROW_LAST) rc = launch_grouped_pass(b, mode, TASK_COL);
+        return rc;
     }
     for (auto& g : b->grp) {
         const bool last = mode == ROW_LAST;
@@ -415,7 +426,13 @@ int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count) {
         BatchGroup bg;
         bg.g = best;
         bg.cav = kv.second;
-        for (int v = 0; v < best->nvariants; ++v) bg.occ[v] = best->var[v].occupancy();
+        for (int v = 0; v < best->nvariants; ++v) {
+            bg.occ[v] = best->var[v].occupancy();
+            if (best->var[v].occupancy_pipe) {
+                bg.occ_pipe[v][TASK_ROW] = best->var[v].occupancy_pipe(TASK_ROW);
+                bg.occ_pipe[v][TASK_COL] = best->var[v].occupancy_pipe(TASK_COL);
+            }
+        }
         const size_t ncav = bg.cav.size();
         if (hipMalloc(&bg.d_desc, ncav * sizeof(CavDesc)) != hipSuccess ||
             hipMalloc(&bg.d_ctrl, (CTRL_ROWDONE + ncav) * sizeof(unsigned)) != hipSuccess) {
@@ -451,7 +468,7 @@ int lsr_batch_set_graph_trips(lsr_batch b, int k) {
 int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, int chunk, int lag, int graph_k,
                         int* cfg_out) {
     if (!b) return set_err(LSR_EINVAL, "batch is NULL");
-    if (engine > 1 || variant > 3 || chunk == 0 || chunk > 1024)
+    if (engine > 2 || variant > 3 || chunk == 0 || chunk > 1024)
         return set_err(LSR_EINVAL, "bad batch configuration");
     DeviceGuard dg(b->device);
     Tune t = b->tune;
@@ -521,21 +538,14 @@ int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* N, int n_tr
                 if (x) (void)hipEventDestroy(x);
             return set_err(LSR_EDEVICE, "hipEventCreate failed");
         }
-    const bool grouped = b->tune.engine == 1;
+    const bool grouped = b->tune.engine >= 1;
     for (int t = 0; t <= n_trips && rc == LSR_OK; ++t) {
         const int mode = t == 0 ? ROW_FIRST : (t == n_trips ? ROW_LAST : ROW_MID);
         (void)hipEventRecord(ev[3 * t], b->stream);
         if (grouped) {
-            for (auto& g : b->grp)
-                if (rc == LSR_OK && g.g->var[variant_of(b, g)].launch_pass(mode, TASK_ROW, b->stream, g.d_desc,
-                                                                          g.d_last, g.nlast))
-                    rc = set_err(LSR_EDEVICE, "row-pass launch failed");
+            rc = launch_grouped_pass(b, mode, TASK_ROW);
             (void)hipEventRecord(ev[3 * t + 1], b->stream);
-            if (mode != ROW_LAST)
-                for (auto& g : b->grp)
-                    if (rc == LSR_OK && g.g->var[variant_of(b, g)].launch_pass(mode, TASK_COL, b->stream,
-                                                                              g.d_desc, g.d_cols, g.ncols))
-                        rc = set_err(LSR_EDEVICE, "column-pass launch failed");
+            if (rc == LSR_OK && mode != ROW_LAST) rc = launch_grouped_pass(b, mode, TASK_COL);
         } else {
             rc = launch_trip(b, mode);
             (void)hipEventRecord(ev[3 * t + 1], b->stream);
@@ -636,19 +646,21 @@ int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
     const int trips = pts_total > 32L * 1024 * 1024 ? 6 : 24;
     int nvar = 1;
     for (auto& g : b->grp) nvar = std::max(nvar, g.g->nvariants);
-    // grouped launches: the register budget is the only choice
-    for (int v = 0; v < nvar; ++v) {
-        b->tune.engine = 1;
-        b->tune.variant = v;
-        b->tune.graph_k = 16;
-        drop_graph(b);
-        if (batch_pack(b)) continue;
-        const double ms = time_batch(b, E, N, trips);
-        if (ms > 0 && ms < best_ms) {
-            best_ms = ms;
-            best = b->tune;
+    // grouped launches, plain and software-pipelined: the register budget
+    // is the only other choice
+    for (int eng : {2, 1})
+        for (int v = 0; v < nvar; ++v) {
+            b->tune.engine = eng;
+            b->tune.variant = v;
+            b->tune.graph_k = 16;
+            drop_graph(b);
+            if (batch_pack(b)) continue;
+            const double ms = time_batch(b, E, N, trips);
+            if (ms > 0 && ms < best_ms) {
+                best_ms = ms;
+                best = b->tune;
+            }
         }
-    }
     for (int v = 0; v < nvar; ++v) {
         int occ = 1;
         for (auto& g : b->grp) occ = std::max(occ, g.occ[v < g.g->nvariants ? v : 0]);

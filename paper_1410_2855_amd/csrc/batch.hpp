@@ -20,6 +20,10 @@ struct KernelVariant {
     int (*launch_pass)(int mode, int kind, hipStream_t st, const CavDesc* descs, const int4* tasks, int ntasks);
     int (*occupancy)();
     int waves_per_eu;    // register budget the variant was compiled for
+    // software-pipelined grouped pass (single-size groups only; else null)
+    int (*launch_pipe)(int mode, int kind, hipStream_t st, const CavDesc* descs, const int4* tasks, int ntasks,
+                       int grid);
+    int (*occupancy_pipe)(int kind);
 };
 
 struct GroupInfo {

@@ -132,6 +132,71 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
     (run_if<MODE, Ss>(d, KIND, blk, smem, red) || ...);
 }
 
+// Software-pipelined grouped pass for a single grid size: a resident grid
+// walks the pass's tasks with a static stride (tasks of one pass are
+// independent) and issues the global loads of its next task as soon as the
+// current task's tile is in LDS, so HBM traffic overlaps the FFT work.  The
+// body must then issue no global load it waits for (a wait would also wait
+// for the prefetch): twiddles live in LDS for the whole kernel, and the
+// column pass's propagator table travels with the prefetched tile.
+template <class S>
+constexpr int pipe_lds_bytes(int kind) {
+    return S::LDS_ELEMS * 8 + S::TW_TOTAL * 8 + (kind == TASK_COL ? S::N * 8 : 0);
+}
+
+template <int MODE, int KIND, int THREADS, int WPE, class S>
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_pass_pipe(
+    const CavDesc* __restrict__ descs, const int4* __restrict__ tasks, int ntasks) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[pipe_lds_bytes<S>(KIND)];
+    __shared__ double red[4 * 16];
+    cx<float>* lds = reinterpret_cast<cx<float>*>(smem);
+    cx<float>* ltw = lds + S::LDS_ELEMS;
+    cx<float>* lhx = ltw + S::TW_TOTAL;
+    int t = blockIdx.x;
+    if (t >= ntasks) return;
+    int cav = __builtin_amdgcn_readfirstlane(tasks[t].x);
+    int blk = __builtin_amdgcn_readfirstlane(tasks[t].z);
+    // every cavity of the group has the same N and precision: same twiddles
+    twiddles_to_lds<S, float>(static_cast<const cx<float>*>(descs[cav].tw), ltw, opaque_tid());
+    if constexpr (KIND == TASK_ROW) {
+        RowRegs<S, float> in;
+        row_load<S, float, MODE>(descs[cav], blk, in);
+        for (;;) {
+            const int tn = t + (int)gridDim.x;
+            const bool more = tn < ntasks;
+            const int cavn = more ? __builtin_amdgcn_readfirstlane(tasks[tn].x) : 0;
+            const int blkn = more ? __builtin_amdgcn_readfirstlane(tasks[tn].z) : 0;
+            row_body<S, float, MODE, TW_LDS>(descs[cav], blk, lds, red, in, [&] {
+                if (more) row_load<S, float, MODE>(descs[cavn], blkn, in);
+            }, ltw);
+            if (!more) break;
+            t = tn;
+            cav = cavn;
+            blk = blkn;
+            __syncthreads();
+        }
+    } else {
+        ColRegs<S, float, true> in;
+        col_load<S, float, COL_PROP, true>(descs[cav], blk, in);
+        for (;;) {
+            const int tn = t + (int)gridDim.x;
+            const bool more = tn < ntasks;
+            const int cavn = more ? __builtin_amdgcn_readfirstlane(tasks[tn].x) : 0;
+            const int blkn = more ? __builtin_amdgcn_readfirstlane(tasks[tn].z) : 0;
+            const CavDesc& d = descs[cav];
+            if (blk == 0 && threadIdx.x < 64) finalize_sums(d);
+            col_body<S, float, COL_PROP, PROP_TABLE, TW_LDS, true>(d, blk, lds, in, [&] {
+                if (more) col_load<S, float, COL_PROP, true>(descs[cavn], blkn, in);
+            }, ltw, lhx);
+            if (!more) break;
+            t = tn;
+            cav = cavn;
+            blk = blkn;
+            __syncthreads();
+        }
+    }
+}
+
 template <int WPE, class... Ss>
 struct GroupKernels {
     static constexpr int THREADS = Group<Ss...>::THREADS;
@@ -170,7 +235,47 @@ struct GroupKernels {
         }
         return hipGetLastError() == hipSuccess ? 0 : -3;
     }
-    static KernelVariant variant() { return KernelVariant{&launch, &launch_pass, &occupancy, WPE}; }
+    // pipelined pass (single-size groups): resident grid of `grid` workgroups
+    static int launch_pipe(int mode, int kind, hipStream_t st, const CavDesc* descs, const int4* tasks,
+                           int ntasks, int grid) {
+        if constexpr (sizeof...(Ss) == 1) {
+            const dim3 g(grid < ntasks ? grid : ntasks), b(THREADS);
+            if (kind == TASK_COL) {
+                hipLaunchKernelGGL((k_pass_pipe<ROW_MID, TASK_COL, THREADS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks);
+            } else {
+                switch (mode) {
+                case ROW_FIRST: hipLaunchKernelGGL((k_pass_pipe<ROW_FIRST, TASK_ROW, THREADS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks); break;
+                case ROW_MID:   hipLaunchKernelGGL((k_pass_pipe<ROW_MID, TASK_ROW, THREADS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks); break;
+                case ROW_LAST:  hipLaunchKernelGGL((k_pass_pipe<ROW_LAST, TASK_ROW, THREADS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks); break;
+                default: return -1;
+                }
+            }
+            return hipGetLastError() == hipSuccess ? 0 : -3;
+        } else {
+            return -1;
+        }
+    }
+    // resident workgroups per CU of the pipelined row (kind 0) / column pass
+    static int occupancy_pipe(int kind) {
+        if constexpr (sizeof...(Ss) == 1) {
+            int n = 0;
+            hipError_t e = kind == TASK_COL
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pass_pipe<ROW_MID, TASK_COL, THREADS, WPE, Ss...>, THREADS, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pass_pipe<ROW_MID, TASK_ROW, THREADS, WPE, Ss...>, THREADS, 0);
+            return (e == hipSuccess && n > 0) ? n : 1;
+        } else {
+            (void)kind;
+            return 0;
+        }
+    }
+    static KernelVariant variant() {
+        KernelVariant v{&launch, &launch_pass, &occupancy, WPE, nullptr, nullptr};
+        if constexpr (sizeof...(Ss) == 1) {
+            v.launch_pipe = &launch_pipe;
+            v.occupancy_pipe = &occupancy_pipe;
+        }
+        return v;
+    }
 };
 
 template <class... Ss>

@@ -44,7 +44,13 @@ __device__ __forceinline__ cx<T> rot_q(cx<T> a) {
 // 64-bit address each; the cast to the global address space and the 32-bit
 // offset let it use global_load/store with a scalar base and a 32-bit vector
 // offset.  A cavity's arrays are far below 4 GiB.
+// (The host pass of this single-source file parses device functions too;
+// there the qualifier is dropped.)
+#if defined(__HIP_DEVICE_COMPILE__)
 #define LSR_GLOBAL __attribute__((address_space(1)))
+#else
+#define LSR_GLOBAL
+#endif
 // CST is a compile-time byte offset applied on the pointer side, so it folds
 // into the instruction's immediate offset.
 template <typename V, int CST = 0>

@@ -140,8 +140,16 @@ __device__ __forceinline__ void load_tw(cx<T>* w, const cx<T>* __restrict__ tw, 
     }
 }
 
+// Where the Stockham twiddles come from: TW_GLOBAL reads the plan's table in
+// HBM (k-major, 16-byte loads per lane); TW_LDS reads a copy held in LDS in
+// r-major order (entry r*Ns + k of a segment), so the lanes of a wave read
+// consecutive entries.  Kernels that keep global loads in flight across the
+// FFT use TW_LDS: on this ISA waiting for a later global load also waits for
+// every earlier one.
+enum : int { TW_GLOBAL = 0, TW_LDS = 1 };
+
 // Butterflies of pass PASS in direction DIR on the lane's registers.
-template <class S, int DIR, int PASS, typename T>
+template <class S, int DIR, int PASS, int TWS = TW_GLOBAL, typename T>
 __device__ __forceinline__ void pass_compute(cx<T>* v, int lane, const cx<T>* __restrict__ tw) {
     constexpr int R = S::rad(DIR, PASS);
     constexpr int Ns = S::ns(DIR, PASS);
@@ -153,13 +161,38 @@ __device__ __forceinline__ void pass_compute(cx<T>* v, int lane, const cx<T>* __
             const int j = lane + b * S::L;
             const int k = j % Ns;
             cx<T> w[R];
-            load_tw<R, S::tw_off(DIR, PASS)>(w, tw, k);
+            if constexpr (TWS == TW_LDS) {
+                sfor<1, R>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    w[r] = tw[S::tw_off(DIR, PASS) + r * Ns + k];
+                });
+            } else {
+                load_tw<R, S::tw_off(DIR, PASS)>(w, tw, k);
+            }
             sfor<1, R>([&](auto rc) {
                 constexpr int r = decltype(rc)::value;
                 x[r] = cmul(x[r], w[r]);
             });
         }
         dft<R, DIR>(x);
+    });
+}
+
+// Copy a twiddle table from HBM (k-major segments) into LDS (r-major).
+template <class S, typename T>
+__device__ __forceinline__ void twiddles_to_lds(const cx<T>* __restrict__ tw, cx<T>* ltw, int tid) {
+    sfor<0, 2 * S::NP>([&](auto pc) {
+        constexpr int dir = decltype(pc)::value < S::NP ? FWD : INV;
+        constexpr int pass = decltype(pc)::value % S::NP;
+        constexpr int Ns = S::ns(dir, pass);
+        constexpr int R = S::rad(dir, pass);
+        constexpr int off = S::tw_off(dir, pass);
+        if constexpr (Ns > 1) {
+            for (int i = tid; i < Ns * R; i += S::THREADS) {
+                const int k = i / R, r = i % R;
+                ltw[off + r * Ns + k] = gld<cx<T>>(tw, (unsigned)(sizeof(cx<T>) * (off + i)));
+            }
+        }
     });
 }
 
@@ -246,11 +279,11 @@ template <class S> constexpr int R_LAST = S::rad_fwd(S::NP - 1);
 // (gather_in order for the first radix of DIR); on exit the natural-order
 // outputs in the gather_in order of the last radix of DIR.  The line buffer
 // is scratch; the caller synchronises before reusing it.
-template <class S, int DIR, typename T>
+template <class S, int DIR, int TWS = TW_GLOBAL, typename T>
 __device__ __forceinline__ void fft_line(cx<T>* v, cx<T>* line, int lane, const cx<T>* __restrict__ tw) {
     sfor<0, S::NP>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
-        pass_compute<S, DIR, p>(v, lane, tw);
+        pass_compute<S, DIR, p, TWS>(v, lane, tw);
         if constexpr (p + 1 < S::NP) {
             pass_scatter<S, DIR, p>(v, line, lane);
             line_sync<S>();

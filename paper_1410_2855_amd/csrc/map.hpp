@@ -92,18 +92,22 @@ __device__ __forceinline__ void row_chunk_pos(int c, int& l, int& x) {
     }
 }
 
-template <class S, typename T, int LAYOUT>
-__device__ __forceinline__ void stage_in_rows(const cx<T>* __restrict__ blk, cx<T>* lds, int tid) {
+// Chunks of a row span a workgroup thread stages.
+template <class S, typename T> constexpr int ROW_IT = S::LPW * S::N / EPC<T> / S::THREADS;
+
+template <class S, typename T>
+__device__ __forceinline__ void load_rows(const cx<T>* __restrict__ blk, typename V16<T>::type* q, int tid) {
     using V = typename V16<T>::type;
-    constexpr int NCH = S::LPW * S::N / EPC<T>;
-    static_assert(NCH % S::THREADS == 0, "row staging must tile the workgroup");
-    constexpr int IT = NCH / S::THREADS;
-    V q[IT];
-    sfor<0, IT>([&](auto ic) {
+    static_assert((S::LPW * S::N / EPC<T>) % S::THREADS == 0, "row staging must tile the workgroup");
+    sfor<0, ROW_IT<S, T>>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         q[i] = gld<V, 16 * i * S::THREADS>(blk, 16u * (unsigned)tid);
     });
-    sfor<0, IT>([&](auto ic) {
+}
+
+template <class S, typename T, int LAYOUT>
+__device__ __forceinline__ void commit_rows(const typename V16<T>::type* q, cx<T>* lds, int tid) {
+    sfor<0, ROW_IT<S, T>>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         int l, x;
         row_chunk_pos<S, T, LAYOUT>(tid + i * S::THREADS, l, x);
@@ -143,29 +147,32 @@ __device__ __forceinline__ unsigned col_chunk(int c, int& line, int& y) {
     return (unsigned)(i * S::LPW * S::N + o) / EPC<T>;
 }
 
+template <class S, typename T> constexpr int COL_IT = S::N * S::LPW / EPC<T> / S::THREADS;
+
 template <class S, typename T>
-__device__ __forceinline__ void stage_in_cols(const cx<T>* __restrict__ E, int cb, cx<T>* lds, int tid) {
+__device__ __forceinline__ void load_cols(const cx<T>* __restrict__ E, int cb, typename V16<T>::type* q, int tid) {
     using V = typename V16<T>::type;
     static_assert(S::LPW % EPC<T> == 0, "a chunk must stay inside one tile row");
-    constexpr int NCH = S::N * S::LPW / EPC<T>;
-    static_assert(NCH % S::THREADS == 0, "column staging must tile the workgroup");
-    constexpr int IT = NCH / S::THREADS;
+    static_assert((S::N * S::LPW / EPC<T>) % S::THREADS == 0, "column staging must tile the workgroup");
     const cx<T>* src = E + (size_t)cb * S::LPW * S::LPW;
-    V q[IT];
-    unsigned off[IT];
-    int ln[IT], yy[IT];
-    sfor<0, IT>([&](auto ic) {
+    sfor<0, COL_IT<S, T>>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        off[i] = col_chunk<S, T>(tid + i * S::THREADS, ln[i], yy[i]);
+        int ln, yy;
+        q[i] = gld<V>(src, 16u * col_chunk<S, T>(tid + i * S::THREADS, ln, yy));
     });
-    sfor<0, IT>([&](auto ic) { q[decltype(ic)::value] = gld<V>(src, 16u * off[decltype(ic)::value]); });
-    sfor<0, IT>([&](auto ic) {
+}
+
+template <class S, typename T>
+__device__ __forceinline__ void commit_cols(const typename V16<T>::type* q, cx<T>* lds, int tid) {
+    sfor<0, COL_IT<S, T>>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
+        int ln, yy;
+        (void)col_chunk<S, T>(tid + i * S::THREADS, ln, yy);
         cx<T> e[EPC<T>];
         unpack16<T>(q[i], e);
         sfor<0, EPC<T>>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            lds[(ln[i] + k) * S::LINE + S::pad(yy[i])] = e[k];
+            lds[(ln + k) * S::LINE + S::pad(yy)] = e[k];
         });
     });
 }
@@ -315,37 +322,60 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
 }
 
 // ---------------------------------------------------------------------------
+// A task is split into its global loads (into registers) and its body, so a
+// software-pipelined kernel can issue the next task's loads while the body of
+// the current one runs.  The body calls prefetch() once the loaded tile is in
+// LDS and the registers are free again.
+template <class S, typename T>
+struct RowRegs {
+    typename V16<T>::type q[ROW_IT<S, T>];
+    T nv[S::P];
+};
+
 template <class S, typename T, int MODE>
-__device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, double* red) {
+__device__ __forceinline__ void row_load(const CavDesc& d, int rb, RowRegs<S, T>& in) {
     const int tid = opaque_tid();
     const int line = tid / S::L, lane = tid % S::L;
     const int y = rb * S::LPW + line;
-    cx<T>* blk = static_cast<cx<T>*>(d.E) + (size_t)rb * S::LPW * S::N;
-    const cx<T>* tw = static_cast<const cx<T>*>(d.tw);
-    cx<T>* myl = lds + line * S::LINE;
     constexpr int RF = R_FIRST<S>;
-    constexpr int RL = R_LAST<S>;
-
-    T nv[S::P];
     if constexpr (MODE != ROW_LAST) {
         const unsigned row = (unsigned)y * (unsigned)S::N * (unsigned)sizeof(T);
         sfor<0, S::P / RF>([&](auto bc) {
             sfor<0, RF>([&](auto rc) {
                 constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
-                nv[b * RF + r] = gld<T, (int)sizeof(T) * (b * S::L + r * (S::N / RF))>(
+                in.nv[b * RF + r] = gld<T, (int)sizeof(T) * (b * S::L + r * (S::N / RF))>(
                     d.Ninv, row + (unsigned)sizeof(T) * (unsigned)lane);
             });
         });
     }
-    if constexpr (MODE == ROW_FIRST || MODE == ROW_DIAG) stage_in_rows<S, T, 0>(blk, lds, tid);
-    else stage_in_rows<S, T, 1>(blk, lds, tid);
+    load_rows<S, T>(static_cast<const cx<T>*>(d.E) + (size_t)rb * S::LPW * S::N, in.q, tid);
+}
+
+// TWS / ltw: twiddle source (TW_LDS: ltw is the workgroup's LDS copy).
+template <class S, typename T, int MODE, int TWS = TW_GLOBAL, class Prefetch>
+__device__ __forceinline__ void row_body(const CavDesc& d, int rb, cx<T>* lds, double* red, RowRegs<S, T>& in,
+                                         Prefetch&& prefetch, const cx<T>* ltw = nullptr) {
+    const int tid = opaque_tid();
+    const int line = tid / S::L, lane = tid % S::L;
+    const int y = rb * S::LPW + line;
+    cx<T>* blk = static_cast<cx<T>*>(d.E) + (size_t)rb * S::LPW * S::N;
+    const cx<T>* tw = TWS == TW_LDS ? ltw : static_cast<const cx<T>*>(d.tw);
+    cx<T>* myl = lds + line * S::LINE;
+    constexpr int RF = R_FIRST<S>;
+    constexpr int RL = R_LAST<S>;
+
+    T nv[S::P];
+    if constexpr (MODE != ROW_LAST) sfor<0, S::P>([&](auto ic) { nv[decltype(ic)::value] = in.nv[decltype(ic)::value]; });
+    if constexpr (MODE == ROW_FIRST || MODE == ROW_DIAG) commit_rows<S, T, 0>(in.q, lds, tid);
+    else commit_rows<S, T, 1>(in.q, lds, tid);
     __syncthreads();
+    prefetch();
 
     cx<T> v[S::P];
     if constexpr (MODE == ROW_MID || MODE == ROW_LAST) {
         gather_in<S, RL>(v, myl, lane);
         line_sync<S>();
-        fft_line<S, INV>(v, myl, lane, tw);
+        fft_line<S, INV, TWS>(v, myl, lane, tw);
     } else {
         gather_in<S, RF>(v, myl, lane);
         line_sync<S>();
@@ -362,7 +392,7 @@ __device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, d
         local_step<S, T, MODE>(v, nv, d, y, lane, acc);
         double accd[4] = {(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
         block_sums_store<S>(accd, red, d.partials + 4 * rb, tid);
-        fft_line<S, FWD>(v, myl, lane, tw);
+        fft_line<S, FWD, TWS>(v, myl, lane, tw);
         scatter_out<S, RL>(v, myl, lane);
         __syncthreads();
         cx<T>* dst = blk;
@@ -371,28 +401,78 @@ __device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, d
     }
 }
 
+template <class S, typename T, int MODE>
+__device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, double* red) {
+    RowRegs<S, T> in;
+    row_load<S, T, MODE>(d, rb, in);
+    row_body<S, T, MODE>(d, rb, lds, red, in, [] {});
+}
+
 // PROP: propagator form of the column pass -- PROP_TABLE multiplies by the
 // FP64-built separable table hx(p) hx(q); PROP_PHASE evaluates the phase
 // pi lambda L (fx^2 + fy^2) in the field's precision (the plain form).
 enum : int { PROP_TABLE = 0, PROP_PHASE = 1 };
 
-template <class S, typename T, int MODE, int PROP = PROP_TABLE>
-__device__ __forceinline__ void col_task(const CavDesc& d, int cb, cx<T>* lds) {
+// Column-task registers; with HXREG the task's propagator table hx travels
+// with the tile (HX_IT 16-byte chunks per thread) and is committed to LDS.
+template <class S, typename T> constexpr int HX_IT = (S::N * (int)sizeof(cx<T>) / 16 + S::THREADS - 1) / S::THREADS;
+
+template <class S, typename T, bool HXREG = false>
+struct ColRegs {
+    typename V16<T>::type q[COL_IT<S, T>];
+    typename V16<T>::type hq[HXREG ? HX_IT<S, T> : 1];
+};
+
+template <class S, typename T, int MODE, bool HXREG = false>
+__device__ __forceinline__ void col_load(const CavDesc& d, int cb, ColRegs<S, T, HXREG>& in) {
+    const int tid = opaque_tid();
+    const cx<T>* E = static_cast<const cx<T>*>(MODE == COL_DIAG ? d.scratch : d.E);
+    load_cols<S, T>(E, cb, in.q, tid);
+    if constexpr (HXREG) {
+        using V = typename V16<T>::type;
+        constexpr int NCH = S::N * (int)sizeof(cx<T>) / 16;
+        sfor<0, HX_IT<S, T>>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const int c = tid + i * S::THREADS;
+            if (NCH % S::THREADS == 0 || c < NCH) in.hq[i] = gld<V>(d.hx, 16u * (unsigned)c);
+        });
+    }
+}
+
+// TWS / ltw: twiddle source; HXREG / lhx: the propagator table comes from the
+// task registers through the LDS buffer lhx (N entries).
+template <class S, typename T, int MODE, int PROP, int TWS = TW_GLOBAL, bool HXREG = false, class Prefetch>
+__device__ __forceinline__ void col_body(const CavDesc& d, int cb, cx<T>* lds, ColRegs<S, T, HXREG>& in,
+                                         Prefetch&& prefetch, const cx<T>* ltw = nullptr, cx<T>* lhx = nullptr) {
     const int tid = opaque_tid();
     const int line = tid / S::L, lane = tid % S::L;
     cx<T>* E = static_cast<cx<T>*>(MODE == COL_DIAG ? d.scratch : d.E);
-    const cx<T>* tw = static_cast<const cx<T>*>(d.tw);
+    const cx<T>* tw = TWS == TW_LDS ? ltw : static_cast<const cx<T>*>(d.tw);
     cx<T>* myl = lds + line * S::LINE;
     constexpr int RF = R_FIRST<S>;
     constexpr int RL = R_LAST<S>;
     constexpr int B = S::P / RL;
 
-    stage_in_cols<S, T>(E, cb, lds, tid);
+    commit_cols<S, T>(in.q, lds, tid);
+    if constexpr (HXREG) {
+        using V = typename V16<T>::type;
+        constexpr int NCH = S::N * (int)sizeof(cx<T>) / 16;
+        sfor<0, HX_IT<S, T>>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const int c = tid + i * S::THREADS;
+            if (NCH % S::THREADS == 0 || c < NCH) {
+                cx<T> e[EPC<T>];
+                unpack16<T>(in.hq[i], e);
+                sfor<0, EPC<T>>([&](auto kc) { lhx[c * EPC<T> + decltype(kc)::value] = e[decltype(kc)::value]; });
+            }
+        });
+    }
     __syncthreads();
+    prefetch();
     cx<T> v[S::P];
     gather_in<S, RF>(v, myl, lane);
     line_sync<S>();
-    fft_line<S, FWD>(v, myl, lane, tw);
+    fft_line<S, FWD, TWS>(v, myl, lane, tw);
     const int kx = cb * S::LPW + line;
     const int px = signed_idx(kx, S::N);
 
@@ -426,6 +506,14 @@ __device__ __forceinline__ void col_task(const CavDesc& d, int cb, cx<T>* lds) {
                     v[b * RL + r] = cmul(v[b * RL + r], cx<T>{co * inn, -s * inn});
                 });
             });
+        } else if constexpr (HXREG) {
+            const cx<T> hk = lhx[kx];
+            sfor<0, B>([&](auto bc) {
+                sfor<0, RL>([&](auto rc) {
+                    constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
+                    v[b * RL + r] = cmul(v[b * RL + r], cmul(hk, lhx[reg_pos<S, RL>(lane, b, r)]));
+                });
+            });
         } else {
             const cx<T>* hx = static_cast<const cx<T>*>(d.hx);
             const cx<T> hk = gld<cx<T>>(hx, (unsigned)sizeof(cx<T>) * (unsigned)kx);
@@ -437,11 +525,18 @@ __device__ __forceinline__ void col_task(const CavDesc& d, int cb, cx<T>* lds) {
                 });
             });
         }
-        fft_line<S, INV>(v, myl, lane, tw);
+        fft_line<S, INV, TWS>(v, myl, lane, tw);
         scatter_out<S, RF>(v, myl, lane);
         __syncthreads();
         stage_out_cols<S, T>(E, cb, lds, tid);
     }
+}
+
+template <class S, typename T, int MODE, int PROP = PROP_TABLE>
+__device__ __forceinline__ void col_task(const CavDesc& d, int cb, cx<T>* lds) {
+    ColRegs<S, T> in;
+    col_load<S, T, MODE>(d, cb, in);
+    col_body<S, T, MODE, PROP>(d, cb, lds, in, [] {});
 }
 
 }  // namespace lsr

@@ -48,19 +48,24 @@ def mixed(count, sizes):
     return cavs
 
 
-@pytest.mark.parametrize("sizes,count,trips,k", [
-    ((256, 384, 512, 768, 1024), 9, 13, 4),     # mixed group, graph + remainder
-    ((1024,), 5, 7, 0),                          # single-size group, eager
-    ((1024,), 3, 1, 16),                         # one trip: FIRST + LAST only
-    ((2048,), 2, 5, 2),
-    ((256, 2048), 4, 6, 3),                      # 256..2048 group
-    ((4096, 512), 2, 3, 1),                      # two workgroup sizes: two groups
+@pytest.mark.parametrize("sizes,count,trips,k,engine", [
+    ((256, 384, 512, 768, 1024), 9, 13, 4, 2),  # mixed group, graph + remainder
+    ((256, 384, 512, 768, 1024), 5, 6, 2, 0),   # mixed group, persistent kernel
+    ((1024,), 5, 7, 0, 2),                       # single-size group, pipelined, eager
+    ((1024,), 5, 7, 3, 1),                       # grouped, not pipelined
+    ((1024,), 4, 5, 2, 0),                       # persistent kernel
+    ((1024,), 3, 1, 16, 2),                      # one trip: FIRST + LAST only
+    ((2048,), 2, 5, 2, 2),
+    ((256, 2048), 4, 6, 3, 2),                   # 256..2048 group
+    ((4096, 512), 2, 3, 1, 2),                   # two workgroup sizes: two groups
+    ((384,), 7, 4, 2, 2),
 ])
-def test_batch_is_bitwise_the_plain_path(sizes, count, trips, k):
+def test_batch_is_bitwise_the_plain_path(sizes, count, trips, k, engine):
     cavs = mixed(count, sizes)
     ref, ref_tr = plain_reference(cavs, trips)
     plans, Es, Ns = make(cavs)
     b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_configure(b, engine=engine)
     lsr.lsr_batch_set_graph_trips(b, k)
     lsr.lsr_batch_roundtrips(b, Es, Ns, trips)
     for p in plans:
