@@ -117,10 +117,24 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
 
 // Grouped launch: one workgroup per task of one pass (all row blocks, or
 // all column blocks, of every cavity); the kernel boundary orders the passes.
+// Column tasks of single-size groups bring the cavity's propagator table hx
+// into LDS together with their tile, so the propagator multiply in the middle
+// of the transforms reads LDS instead of waiting on global loads.
+template <class S>
+__device__ __forceinline__ void col_task_hx_lds(const CavDesc& d, int cb, unsigned char* smem) {
+    cx<float>* lds = reinterpret_cast<cx<float>*>(smem);
+    ColRegs<S, float, true> in;
+    col_load<S, float, COL_PROP, true>(d, cb, in);
+    col_body<S, float, COL_PROP, PROP_TABLE, TW_GLOBAL, true>(d, cb, lds, in, [] {}, nullptr,
+                                                               lds + S::LDS_ELEMS);
+}
+
 template <int MODE, int KIND, int THREADS, int LDS_BYTES, int WPE, class... Ss>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_pass(
     const CavDesc* __restrict__ descs, const int4* __restrict__ tasks) {
-    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
+    constexpr bool HXLDS = sizeof...(Ss) == 1 && KIND == TASK_COL &&
+                           LDS_BYTES + ((Ss::N * 8) + ... + 0) + 4 * 16 * 8 <= 160 * 1024;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES + (HXLDS ? ((Ss::N * 8) + ...) : 0)];
     __shared__ double red[4 * 16];
     const int4 tk = tasks[blockIdx.x];
     const int cav = __builtin_amdgcn_readfirstlane(tk.x);
@@ -129,7 +143,8 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
     if constexpr (KIND == TASK_COL) {
         if (blk == 0 && threadIdx.x < 64) finalize_sums(d);
     }
-    (run_if<MODE, Ss>(d, KIND, blk, smem, red) || ...);
+    if constexpr (HXLDS) (col_task_hx_lds<Ss>(d, blk, smem), ...);
+    else (run_if<MODE, Ss>(d, KIND, blk, smem, red) || ...);
 }
 
 // Software-pipelined grouped pass for a single grid size: a resident grid
@@ -197,10 +212,21 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
     }
 }
 
+template <class... Ss>
+constexpr bool pipe_fits() {
+    if constexpr (sizeof...(Ss) == 1)
+        return ((pipe_lds_bytes<Ss>(TASK_COL) + 4 * 16 * 8 <= 160 * 1024) && ...);
+    else
+        return false;
+}
+
 template <int WPE, class... Ss>
 struct GroupKernels {
     static constexpr int THREADS = Group<Ss...>::THREADS;
     static constexpr int LDS = Group<Ss...>::maxl();
+    // the pipelined pass exists for single-size groups whose LDS (lines,
+    // twiddles, propagator table) fits one workgroup
+    static constexpr bool PIPE = pipe_fits<Ss...>();
 
     static int launch(int mode, int grid, hipStream_t st, const CavDesc* descs, const int4* tasks,
                       int ntasks, unsigned* ctrl, int chunk) {
@@ -238,7 +264,7 @@ struct GroupKernels {
     // pipelined pass (single-size groups): resident grid of `grid` workgroups
     static int launch_pipe(int mode, int kind, hipStream_t st, const CavDesc* descs, const int4* tasks,
                            int ntasks, int grid) {
-        if constexpr (sizeof...(Ss) == 1) {
+        if constexpr (PIPE) {
             const dim3 g(grid < ntasks ? grid : ntasks), b(THREADS);
             if (kind == TASK_COL) {
                 hipLaunchKernelGGL((k_pass_pipe<ROW_MID, TASK_COL, THREADS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks);
@@ -257,7 +283,7 @@ struct GroupKernels {
     }
     // resident workgroups per CU of the pipelined row (kind 0) / column pass
     static int occupancy_pipe(int kind) {
-        if constexpr (sizeof...(Ss) == 1) {
+        if constexpr (PIPE) {
             int n = 0;
             hipError_t e = kind == TASK_COL
                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pass_pipe<ROW_MID, TASK_COL, THREADS, WPE, Ss...>, THREADS, 0)
@@ -270,7 +296,7 @@ struct GroupKernels {
     }
     static KernelVariant variant() {
         KernelVariant v{&launch, &launch_pass, &occupancy, WPE, nullptr, nullptr};
-        if constexpr (sizeof...(Ss) == 1) {
+        if constexpr (PIPE) {
             v.launch_pipe = &launch_pipe;
             v.occupancy_pipe = &occupancy_pipe;
         }

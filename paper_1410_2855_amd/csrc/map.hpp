@@ -455,7 +455,6 @@ __device__ __forceinline__ void col_body(const CavDesc& d, int cb, cx<T>* lds, C
 
     commit_cols<S, T>(in.q, lds, tid);
     if constexpr (HXREG) {
-        using V = typename V16<T>::type;
         constexpr int NCH = S::N * (int)sizeof(cx<T>) / 16;
         sfor<0, HX_IT<S, T>>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
