@@ -55,6 +55,100 @@ def load_traffic(kernel: str, pts_per_launch: int):
     return rec.get("bytes_per_launch")
 
 
+# rocprofv3 commands whose output --summarize turns into the committed
+# summaries under profiles/ (run from /tmp with TMPDIR=/tmp; OUT is a scratch
+# output folder, /root/repo the repository)
+PROFILE_COMMANDS = {
+    "kernel_trace": "rocprofv3 --kernel-trace --stats --output-format csv -d OUT/kt -o kt -- "
+                    "python3 /root/repo/bench.py --steps 200 --warmup 20 --no-cpu-baseline --no-parity",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/pf -o pf -- "
+             "python3 /root/repo/bench.py --profile --steps 2 --warmup 1",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/pw -o pw -- "
+             "python3 /root/repo/bench.py --profile --steps 2 --warmup 1",
+}
+PASS_KERNELS = {"row_pass": "lsr::k_pass<1, 0,", "column_pass": "lsr::k_pass<1, 1,"}
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_BYTES = 64 * 1024 * 1024 * 4   # the calibration copy of --profile, each way
+
+
+def _read_csv(path):
+    import csv
+
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def summarize(out_dir: str, workload: str, cavities: int, grid: int):
+    """Turn rocprofv3 csv output (OUT/kt, OUT/pf, OUT/pw of PROFILE_COMMANDS)
+    into text summaries and profiles/traffic.json.
+
+    HBM traffic per launch = FETCH_SIZE * (copy bytes / copy FETCH_SIZE) +
+    WRITE_SIZE * (copy bytes / copy WRITE_SIZE): both counters are scaled by
+    what they read for the device-to-device copy of COPY_BYTES that
+    bench.py --profile issues."""
+    import glob as _g
+
+    prof = os.path.join(ROOT, "profiles")
+    os.makedirs(prof, exist_ok=True)
+    stats = _read_csv(_g.glob(os.path.join(out_dir, "kt", "*kernel_stats.csv"))[0])
+    pts = cavities * grid * grid
+    counters = {}
+    scale = {}
+    for tag, cname in (("pf", "FETCH_SIZE"), ("pw", "WRITE_SIZE")):
+        rows = _read_csv(_g.glob(os.path.join(out_dir, tag, "*counter_collection.csv"))[0])
+        rows = [r for r in rows if r["Counter_Name"] == cname]
+        copy = max((r for r in rows if COPY_KERNEL in r["Kernel_Name"]), key=lambda r: float(r["Counter_Value"]))
+        scale[cname] = COPY_BYTES / (float(copy["Counter_Value"]) * 1024.0)
+        for k, pat in PASS_KERNELS.items():
+            v = [float(r["Counter_Value"]) for r in rows if pat in r["Kernel_Name"]]
+            counters.setdefault(k, {})[cname] = (sum(v) / len(v), len(v))
+    algo = {"row_pass": ROW_BYTES_PER_PT * pts, "column_pass": COL_BYTES_PER_PT * pts}
+    src = kernel_source_hash()
+    traffic = {}
+    lines_all = ["rocprofv3 kernel statistics: %s" % workload, "",
+                 "command (from /tmp, TMPDIR=/tmp): " + PROFILE_COMMANDS["kernel_trace"], "",
+                 "%-12s %8s %12s %12s %12s  %s" % ("share %", "calls", "avg us", "min us", "max us", "kernel")]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        lines_all.append("%-12.2f %8s %12.2f %12.2f %12.2f  %s" % (
+            float(r["Percentage"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, r["Name"][:160]))
+    with open(os.path.join(prof, "kernel_stats_%dx%d.txt" % (cavities, grid)), "w") as f:
+        f.write("\n".join(lines_all) + "\n")
+    for k, pat in PASS_KERNELS.items():
+        st = [r for r in stats if pat in r["Name"] and ("Shape<%d," % grid) in r["Name"]]
+        if not st:
+            continue
+        r = max(st, key=lambda r: int(r["Calls"]))
+        avg_ms = float(r["AverageNs"]) / 1e6
+        fetch_kib, nf = counters[k]["FETCH_SIZE"]
+        write_kib, nw = counters[k]["WRITE_SIZE"]
+        fb = fetch_kib * 1024 * scale["FETCH_SIZE"]
+        wb = write_kib * 1024 * scale["WRITE_SIZE"]
+        traffic[k] = {"source_hash": src, "points_per_launch": pts, "bytes_per_launch": round(fb + wb),
+                      "fetch_bytes": round(fb), "write_bytes": round(wb), "algorithmic_bytes": algo[k],
+                      "avg_launch_ms": avg_ms}
+        txt = ["%s: %s" % (k, workload), "",
+               "kernel: " + r["Name"], "",
+               "kernel trace (%d calls): avg %.2f us, min %.2f us, max %.2f us" % (
+                   int(r["Calls"]), avg_ms * 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3),
+               "algorithmic bytes per launch: %d (%d B/pt x %d pts) -> %.1f GB/s at the trace average" % (
+                   algo[k], algo[k] // pts, pts, algo[k] / (avg_ms * 1e-3) / 1e9),
+               "",
+               "FETCH_SIZE %.1f KiB/dispatch (%d dispatches), copy-calibrated x%.4f -> %.1f MiB" % (
+                   fetch_kib, nf, scale["FETCH_SIZE"], fb / 2 ** 20),
+               "WRITE_SIZE %.1f KiB/dispatch (%d dispatches), copy-calibrated x%.4f -> %.1f MiB" % (
+                   write_kib, nw, scale["WRITE_SIZE"], wb / 2 ** 20),
+               "HBM traffic per launch %.1f MiB = %.3f x algorithmic" % ((fb + wb) / 2 ** 20, (fb + wb) / algo[k]),
+               "",
+               "commands (from /tmp, TMPDIR=/tmp):"] + ["  " + c for c in PROFILE_COMMANDS.values()] + [
+               "kernel source hash: " + src]
+        with open(os.path.join(prof, "%s_%dx%d.txt" % (k, cavities, grid)), "w") as f:
+            f.write("\n".join(txt) + "\n")
+    with open(os.path.join(prof, "traffic.json"), "w") as f:
+        json.dump(traffic, f, indent=1)
+    print(json.dumps(traffic, indent=1))
+
+
 def cpu_baseline(cav, seconds_target: float = 12.0):
     """The FP64 oracle, single-threaded, on one 1024^2 cavity of the workload:
     as many round trips as fit in about seconds_target."""
@@ -86,7 +180,13 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short batched run for a profiler, plus a copy kernel of known size")
+    ap.add_argument("--summarize", metavar="OUT",
+                    help="write profiles/ summaries from rocprofv3 csv output under OUT (no GPU)")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize, "%d cavities at 1024^2 (sweep parameter draws), FP64-table form"
+                  % args.cavities, args.cavities, 1024)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: every cavity of the workload is independent and the "
               "whole set runs on a single MI355X; sharding across GPUs is a design note, not a run",
