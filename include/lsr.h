@@ -202,11 +202,13 @@ int lsr_batch_set_graph_trips(lsr_batch b, int k);
 int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, int chunk,
                         int lag, int graph_k, int* cfg_out);
 
-/* Profiling form of lsr_batch_roundtrips (eager, no graph): each launch is
- * bracketed by HIP events on the batch's stream.  ms[0] = mean duration of
- * the row-pass launch (all cavities' row blocks of one trip, middle trips
- * only when n_trips > 1), ms[1] = mean column-pass launch, ms[2] = mean
- * round trip (ms[0] + ms[1] + the gaps between them).  With the persistent
+/* Profiling form of lsr_batch_roundtrips (eager, no graph): each pass is
+ * launched with HIP events that the dispatch itself timestamps at kernel
+ * start and end (hipExtLaunchKernelGGL), on the batch's stream.  ms[0] =
+ * mean duration of the row-pass launch (all cavities' row blocks of one
+ * trip, middle trips only when n_trips > 1), ms[1] = mean column-pass
+ * launch, ms[2] = mean round trip from one row-pass start to the next
+ * (ms[0] + ms[1] + the gaps between them).  With the persistent
  * engine the whole trip is one launch: ms[0] = ms[2], ms[1] = 0.
  * Synchronises. */
 int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* Ninv, int n_trips, double* ms);

@@ -245,17 +245,23 @@ static int grid_of(const lsr_batch_s* b, const BatchGroup& g) {
 }
 
 // One grouped pass (kind TASK_ROW or TASK_COL) of every group.
-static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind) {
-    for (auto& g : b->grp) {
+static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind, LaunchEvents ev = {}) {
+    const size_t ng = b->grp.size();
+    for (size_t i = 0; i < ng; ++i) {
+        auto& g = b->grp[i];
         const int v = variant_of(b, g);
         const KernelVariant& kv = g.g->var[v];
         const int4* tasks = kind == TASK_ROW ? g.d_last : g.d_cols;
         const int nt = kind == TASK_ROW ? g.nlast : g.ncols;
+        // timestamps: start of the first group's dispatch, end of the last's
+        LaunchEvents e;
+        if (i == 0) e.start = ev.start;
+        if (i + 1 == ng) e.stop = ev.stop;
         int rc;
         if (b->tune.engine == 2 && kv.launch_pipe)
-            rc = kv.launch_pipe(mode, kind, b->stream, g.d_desc, tasks, nt, g.occ_pipe[v][kind] * b->cus);
+            rc = kv.launch_pipe(mode, kind, b->stream, g.d_desc, tasks, nt, g.occ_pipe[v][kind] * b->cus, e);
         else
-            rc = kv.launch_pass(mode, kind, b->stream, g.d_desc, tasks, nt);
+            rc = kv.launch_pass(mode, kind, b->stream, g.d_desc, tasks, nt, e);
         if (rc)
             return set_err(LSR_EDEVICE, "%s-pass launch failed: %s", kind == TASK_ROW ? "row" : "column",
                            hipGetErrorString(hipGetLastError()));
@@ -263,19 +269,24 @@ static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind) {
     return LSR_OK;
 }
 
-static int launch_trip(lsr_batch_s* b, int mode) {
+static int launch_trip(lsr_batch_s* b, int mode, LaunchEvents ev = {}) {
     if (b->tune.engine >= 1) {
         // grouped: every cavity's row blocks, then every cavity's column blocks
         int rc = launch_grouped_pass(b, mode, TASK_ROW);
         if (rc == LSR_OK && mode != ROW_LAST) rc = launch_grouped_pass(b, mode, TASK_COL);
         return rc;
     }
-    for (auto& g : b->grp) {
+    const size_t ng = b->grp.size();
+    for (size_t i = 0; i < ng; ++i) {
+        auto& g = b->grp[i];
         const bool last = mode == ROW_LAST;
         const int nt = last ? g.nlast : g.ntasks;
         const int grid = std::min(grid_of(b, g), nt);
+        LaunchEvents e;
+        if (i == 0) e.start = ev.start;
+        if (i + 1 == ng) e.stop = ev.stop;
         if (g.g->var[variant_of(b, g)].launch(mode, grid, b->stream, g.d_desc, last ? g.d_last : g.d_tasks, nt,
-                                              g.d_ctrl, last ? 1 : b->tune.chunk))
+                                              g.d_ctrl, last ? 1 : b->tune.chunk, e))
             return set_err(LSR_EDEVICE, "persistent kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     }
     return LSR_OK;
@@ -529,8 +540,9 @@ int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* N, int n_tr
     LSR_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
     int rc = upload_descs(b, E, N, false);
     if (rc) return rc;
-    // per trip: [e0] row [e1] col [e2]; trip t uses events 3t .. 3t+2
-    const int ne = 3 * (n_trips + 1);
+    // dispatch timestamps of trip t: row pass (or persistent trip kernel)
+    // start/stop = events 4t, 4t+1; column pass start/stop = 4t+2, 4t+3
+    const int ne = 4 * (n_trips + 1);
     std::vector<hipEvent_t> ev((size_t)ne, nullptr);
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
@@ -541,26 +553,23 @@ int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* N, int n_tr
     const bool grouped = b->tune.engine >= 1;
     for (int t = 0; t <= n_trips && rc == LSR_OK; ++t) {
         const int mode = t == 0 ? ROW_FIRST : (t == n_trips ? ROW_LAST : ROW_MID);
-        (void)hipEventRecord(ev[3 * t], b->stream);
         if (grouped) {
-            rc = launch_grouped_pass(b, mode, TASK_ROW);
-            (void)hipEventRecord(ev[3 * t + 1], b->stream);
-            if (rc == LSR_OK && mode != ROW_LAST) rc = launch_grouped_pass(b, mode, TASK_COL);
+            rc = launch_grouped_pass(b, mode, TASK_ROW, LaunchEvents{ev[4 * t], ev[4 * t + 1]});
+            if (rc == LSR_OK && mode != ROW_LAST)
+                rc = launch_grouped_pass(b, mode, TASK_COL, LaunchEvents{ev[4 * t + 2], ev[4 * t + 3]});
         } else {
-            rc = launch_trip(b, mode);
-            (void)hipEventRecord(ev[3 * t + 1], b->stream);
+            rc = launch_trip(b, mode, LaunchEvents{ev[4 * t], ev[4 * t + 1]});
         }
-        (void)hipEventRecord(ev[3 * t + 2], b->stream);
     }
     double row = 0, col = 0, trip = 0;
     int nrow = 0;
-    if (rc == LSR_OK && hipEventSynchronize(ev[ne - 1]) == hipSuccess) {
+    if (rc == LSR_OK && hipStreamSynchronize(b->stream) == hipSuccess) {
         for (int t = 0; t < n_trips; ++t) {
             if (n_trips > 1 && t == 0) continue;   // the FIRST form differs
             float a = 0, c = 0, w = 0;
-            (void)hipEventElapsedTime(&a, ev[3 * t], ev[3 * t + 1]);
-            (void)hipEventElapsedTime(&c, ev[3 * t + 1], ev[3 * t + 2]);
-            (void)hipEventElapsedTime(&w, ev[3 * t], ev[3 * t + 3]);
+            (void)hipEventElapsedTime(&a, ev[4 * t], ev[4 * t + 1]);
+            if (grouped) (void)hipEventElapsedTime(&c, ev[4 * t + 2], ev[4 * t + 3]);
+            (void)hipEventElapsedTime(&w, ev[4 * t], ev[4 * t + 4]);
             row += a;
             col += c;
             trip += w;

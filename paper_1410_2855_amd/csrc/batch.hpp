@@ -12,17 +12,25 @@ enum : int { TASK_ROW = 0, TASK_COL = 1 };
 // Control block of a group (device, unsigned words).
 enum : int { CTRL_HEAD = 0, CTRL_EXIT = 1, CTRL_NCAV = 2, CTRL_ABORT = 3, CTRL_ROWDONE = 16 };
 
+// Optional timestamps of one dispatch: when either event is set the launch
+// goes through hipExtLaunchKernelGGL, which records the kernel's own start
+// and end on the events (no gaps of events recorded around it).
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 struct KernelVariant {
     // persistent kernel: one launch per round trip
     int (*launch)(int mode, int grid, hipStream_t st, const CavDesc* descs, const int4* tasks, int ntasks,
-                  unsigned* ctrl, int chunk);
+                  unsigned* ctrl, int chunk, LaunchEvents ev);
     // grouped launch: one launch per pass, one workgroup per task
-    int (*launch_pass)(int mode, int kind, hipStream_t st, const CavDesc* descs, const int4* tasks, int ntasks);
+    int (*launch_pass)(int mode, int kind, hipStream_t st, const CavDesc* descs, const int4* tasks, int ntasks,
+                       LaunchEvents ev);
     int (*occupancy)();
     int waves_per_eu;    // register budget the variant was compiled for
     // software-pipelined grouped pass (single-size groups only; else null)
     int (*launch_pipe)(int mode, int kind, hipStream_t st, const CavDesc* descs, const int4* tasks, int ntasks,
-                       int grid);
+                       int grid, LaunchEvents ev);
     int (*occupancy_pipe)(int kind);
 };
 

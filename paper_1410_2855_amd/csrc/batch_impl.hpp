@@ -16,6 +16,8 @@
 // launch can be replayed from a HIP graph.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include <initializer_list>
 
 #include "batch.hpp"
@@ -133,8 +135,8 @@ template <int MODE, int KIND, int THREADS, int LDS_BYTES, int WPE, class... Ss>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_pass(
     const CavDesc* __restrict__ descs, const int4* __restrict__ tasks) {
     constexpr bool HXLDS = sizeof...(Ss) == 1 && KIND == TASK_COL &&
-                           LDS_BYTES + ((Ss::N * 8) + ... + 0) + 4 * 16 * 8 <= 160 * 1024;
-    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES + (HXLDS ? ((Ss::N * 8) + ...) : 0)];
+                           LDS_BYTES + ((HXN<Ss, float> * 8) + ... + 0) + 4 * 16 * 8 <= 160 * 1024;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES + (HXLDS ? ((HXN<Ss, float> * 8) + ...) : 0)];
     __shared__ double red[4 * 16];
     const int4 tk = tasks[blockIdx.x];
     const int cav = __builtin_amdgcn_readfirstlane(tk.x);
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
 // column pass's propagator table travels with the prefetched tile.
 template <class S>
 constexpr int pipe_lds_bytes(int kind) {
-    return S::LDS_ELEMS * 8 + S::TW_TOTAL * 8 + (kind == TASK_COL ? S::N * 8 : 0);
+    return S::LDS_ELEMS * 8 + S::TW_TOTAL * 8 + (kind == TASK_COL ? HXN<S, float> * 8 : 0);
 }
 
 template <int MODE, int KIND, int THREADS, int WPE, class S>
@@ -220,6 +222,14 @@ constexpr bool pipe_fits() {
         return false;
 }
 
+#define LSR_LAUNCH(KERN, G, B, ST, EV, ...)                                                  \
+    do {                                                                                    \
+        if ((EV).start || (EV).stop)                                                        \
+            hipExtLaunchKernelGGL(KERN, G, B, 0, ST, (EV).start, (EV).stop, 0, __VA_ARGS__); \
+        else                                                                                \
+            hipLaunchKernelGGL(KERN, G, B, 0, ST, __VA_ARGS__);                             \
+    } while (0)
+
 template <int WPE, class... Ss>
 struct GroupKernels {
     static constexpr int THREADS = Group<Ss...>::THREADS;
@@ -229,12 +239,12 @@ struct GroupKernels {
     static constexpr bool PIPE = pipe_fits<Ss...>();
 
     static int launch(int mode, int grid, hipStream_t st, const CavDesc* descs, const int4* tasks,
-                      int ntasks, unsigned* ctrl, int chunk) {
+                      int ntasks, unsigned* ctrl, int chunk, LaunchEvents ev) {
         const dim3 g(grid), b(THREADS);
         switch (mode) {
-        case ROW_FIRST: hipLaunchKernelGGL((k_trip<ROW_FIRST, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks, ctrl, chunk); break;
-        case ROW_MID:   hipLaunchKernelGGL((k_trip<ROW_MID, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks, ctrl, chunk); break;
-        case ROW_LAST:  hipLaunchKernelGGL((k_trip<ROW_LAST, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks, ctrl, chunk); break;
+        case ROW_FIRST: LSR_LAUNCH((k_trip<ROW_FIRST, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks, ntasks, ctrl, chunk); break;
+        case ROW_MID:   LSR_LAUNCH((k_trip<ROW_MID, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks, ntasks, ctrl, chunk); break;
+        case ROW_LAST:  LSR_LAUNCH((k_trip<ROW_LAST, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks, ntasks, ctrl, chunk); break;
         default: return -1;
         }
         return hipGetLastError() == hipSuccess ? 0 : -3;
@@ -247,15 +257,15 @@ struct GroupKernels {
     }
     // grouped launch of one pass: grid = number of tasks of that pass
     static int launch_pass(int mode, int kind, hipStream_t st, const CavDesc* descs, const int4* tasks,
-                           int ntasks) {
+                           int ntasks, LaunchEvents ev) {
         const dim3 g(ntasks), b(THREADS);
         if (kind == TASK_COL) {
-            hipLaunchKernelGGL((k_pass<ROW_MID, TASK_COL, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks);
+            LSR_LAUNCH((k_pass<ROW_MID, TASK_COL, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks);
         } else {
             switch (mode) {
-            case ROW_FIRST: hipLaunchKernelGGL((k_pass<ROW_FIRST, TASK_ROW, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks); break;
-            case ROW_MID:   hipLaunchKernelGGL((k_pass<ROW_MID, TASK_ROW, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks); break;
-            case ROW_LAST:  hipLaunchKernelGGL((k_pass<ROW_LAST, TASK_ROW, THREADS, LDS, WPE, Ss...>), g, b, 0, st, descs, tasks); break;
+            case ROW_FIRST: LSR_LAUNCH((k_pass<ROW_FIRST, TASK_ROW, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks); break;
+            case ROW_MID:   LSR_LAUNCH((k_pass<ROW_MID, TASK_ROW, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks); break;
+            case ROW_LAST:  LSR_LAUNCH((k_pass<ROW_LAST, TASK_ROW, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks); break;
             default: return -1;
             }
         }
@@ -263,21 +273,22 @@ struct GroupKernels {
     }
     // pipelined pass (single-size groups): resident grid of `grid` workgroups
     static int launch_pipe(int mode, int kind, hipStream_t st, const CavDesc* descs, const int4* tasks,
-                           int ntasks, int grid) {
+                           int ntasks, int grid, LaunchEvents ev) {
         if constexpr (PIPE) {
             const dim3 g(grid < ntasks ? grid : ntasks), b(THREADS);
             if (kind == TASK_COL) {
-                hipLaunchKernelGGL((k_pass_pipe<ROW_MID, TASK_COL, THREADS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks);
+                LSR_LAUNCH((k_pass_pipe<ROW_MID, TASK_COL, THREADS, WPE, Ss...>), g, b, st, ev, descs, tasks, ntasks);
             } else {
                 switch (mode) {
-                case ROW_FIRST: hipLaunchKernelGGL((k_pass_pipe<ROW_FIRST, TASK_ROW, THREADS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks); break;
-                case ROW_MID:   hipLaunchKernelGGL((k_pass_pipe<ROW_MID, TASK_ROW, THREADS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks); break;
-                case ROW_LAST:  hipLaunchKernelGGL((k_pass_pipe<ROW_LAST, TASK_ROW, THREADS, WPE, Ss...>), g, b, 0, st, descs, tasks, ntasks); break;
+                case ROW_FIRST: LSR_LAUNCH((k_pass_pipe<ROW_FIRST, TASK_ROW, THREADS, WPE, Ss...>), g, b, st, ev, descs, tasks, ntasks); break;
+                case ROW_MID:   LSR_LAUNCH((k_pass_pipe<ROW_MID, TASK_ROW, THREADS, WPE, Ss...>), g, b, st, ev, descs, tasks, ntasks); break;
+                case ROW_LAST:  LSR_LAUNCH((k_pass_pipe<ROW_LAST, TASK_ROW, THREADS, WPE, Ss...>), g, b, st, ev, descs, tasks, ntasks); break;
                 default: return -1;
                 }
             }
             return hipGetLastError() == hipSuccess ? 0 : -3;
         } else {
+            (void)mode; (void)kind; (void)st; (void)descs; (void)tasks; (void)ntasks; (void)grid; (void)ev;
             return -1;
         }
     }

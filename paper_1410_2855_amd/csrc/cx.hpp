@@ -64,6 +64,35 @@ __device__ __forceinline__ void gst(void* base, unsigned byte_off, const V& v) {
     *(LSR_GLOBAL V*)(b + byte_off) = v;
 }
 
+// Streaming forms for data touched once per pass (the field and the
+// inversion): non-temporal loads and stores, so the stream neither allocates
+// nor keeps lines in the caches that hold the reused tables.  The value goes
+// through the clang vector type of the same size.
+template <typename V> struct NtVec;
+template <> struct NtVec<float> { using type = float; };
+template <> struct NtVec<double> { using type = double; };
+template <> struct NtVec<float4> { using type = float __attribute__((ext_vector_type(4))); };
+template <> struct NtVec<double2> { using type = double __attribute__((ext_vector_type(2))); };
+
+template <typename V, int CST = 0>
+__device__ __forceinline__ V gld_nt(const void* base, unsigned byte_off) {
+    using W = typename NtVec<V>::type;
+    static_assert(sizeof(W) == sizeof(V), "streaming type size");
+    const LSR_GLOBAL char* b = (const LSR_GLOBAL char*)base + CST;
+    const W w = __builtin_nontemporal_load((const LSR_GLOBAL W*)(b + byte_off));
+    V v;
+    __builtin_memcpy(&v, &w, sizeof(V));
+    return v;
+}
+template <typename V, int CST = 0>
+__device__ __forceinline__ void gst_nt(void* base, unsigned byte_off, const V& v) {
+    using W = typename NtVec<V>::type;
+    W w;
+    __builtin_memcpy(&w, &v, sizeof(V));
+    LSR_GLOBAL char* b = (LSR_GLOBAL char*)base + CST;
+    __builtin_nontemporal_store(w, (LSR_GLOBAL W*)(b + byte_off));
+}
+
 // Compile-time loop: f(std::integral_constant<int, i>) for i in [B, E).
 template <int B, int E, class F>
 __device__ __forceinline__ void sfor(F&& f) {

@@ -101,7 +101,7 @@ __device__ __forceinline__ void load_rows(const cx<T>* __restrict__ blk, typenam
     static_assert((S::LPW * S::N / EPC<T>) % S::THREADS == 0, "row staging must tile the workgroup");
     sfor<0, ROW_IT<S, T>>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        q[i] = gld<V, 16 * i * S::THREADS>(blk, 16u * (unsigned)tid);
+        q[i] = gld_nt<V, 16 * i * S::THREADS>(blk, 16u * (unsigned)tid);
     });
 }
 
@@ -129,7 +129,7 @@ __device__ __forceinline__ void stage_out_rows(cx<T>* __restrict__ blk, const cx
         row_chunk_pos<S, T, LAYOUT>(c, l, x);
         cx<T> e[EPC<T>];
         sfor<0, EPC<T>>([&](auto kc) { e[decltype(kc)::value] = lds[l * S::LINE + S::pad(x + decltype(kc)::value)]; });
-        gst<V, 16 * i * S::THREADS>(blk, 16u * (unsigned)tid, pack16<T>(e));
+        gst_nt<V, 16 * i * S::THREADS>(blk, 16u * (unsigned)tid, pack16<T>(e));
     });
 }
 
@@ -158,7 +158,7 @@ __device__ __forceinline__ void load_cols(const cx<T>* __restrict__ E, int cb, t
     sfor<0, COL_IT<S, T>>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         int ln, yy;
-        q[i] = gld<V>(src, 16u * col_chunk<S, T>(tid + i * S::THREADS, ln, yy));
+        q[i] = gld_nt<V>(src, 16u * col_chunk<S, T>(tid + i * S::THREADS, ln, yy));
     });
 }
 
@@ -192,7 +192,7 @@ __device__ __forceinline__ void stage_out_cols(cx<T>* __restrict__ E, int cb, co
             constexpr int k = decltype(kc)::value;
             e[k] = lds[(line + k) * S::LINE + S::pad(y)];
         });
-        gst<V>(dst, 16u * off, pack16<T>(e));
+        gst_nt<V>(dst, 16u * off, pack16<T>(e));
     });
 }
 
@@ -314,7 +314,7 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
             v[i] = g;
             if constexpr (MODE != ROW_DIAG) {
                 const T pump = pc ? N0 * fma_(mamp * gld<T>(pc, (unsigned)sizeof(T) * x), pcy, (T)1) : N0;
-                gst<T, (int)sizeof(T) * (b * S::L + r * (S::N / R))>(
+                gst_nt<T, (int)sizeof(T) * (b * S::L + r * (S::N / R))>(
                     d.Ninv, row + (unsigned)sizeof(T) * (unsigned)lane, fma_(-n, I, fma_(pump - n, iT1, n)));
             }
         });
@@ -343,7 +343,7 @@ __device__ __forceinline__ void row_load(const CavDesc& d, int rb, RowRegs<S, T>
         sfor<0, S::P / RF>([&](auto bc) {
             sfor<0, RF>([&](auto rc) {
                 constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
-                in.nv[b * RF + r] = gld<T, (int)sizeof(T) * (b * S::L + r * (S::N / RF))>(
+                in.nv[b * RF + r] = gld_nt<T, (int)sizeof(T) * (b * S::L + r * (S::N / RF))>(
                     d.Ninv, row + (unsigned)sizeof(T) * (unsigned)lane);
             });
         });
@@ -415,7 +415,11 @@ enum : int { PROP_TABLE = 0, PROP_PHASE = 1 };
 
 // Column-task registers; with HXREG the task's propagator table hx travels
 // with the tile (HX_IT 16-byte chunks per thread) and is committed to LDS.
-template <class S, typename T> constexpr int HX_IT = (S::N * (int)sizeof(cx<T>) / 16 + S::THREADS - 1) / S::THREADS;
+// hx(p) depends on p~^2 only, so the LDS copy keeps entries 0..N/2 (HXN,
+// rounded up to whole 16-byte chunks) and is indexed by |p~|.
+template <class S, typename T> constexpr int HXN = ((S::N / 2 + 1) * (int)sizeof(cx<T>) + 15) / 16 * 16 / (int)sizeof(cx<T>);
+template <class S, typename T> constexpr int HX_CH = HXN<S, T> * (int)sizeof(cx<T>) / 16;
+template <class S, typename T> constexpr int HX_IT = (HX_CH<S, T> + S::THREADS - 1) / S::THREADS;
 
 template <class S, typename T, bool HXREG = false>
 struct ColRegs {
@@ -430,7 +434,7 @@ __device__ __forceinline__ void col_load(const CavDesc& d, int cb, ColRegs<S, T,
     load_cols<S, T>(E, cb, in.q, tid);
     if constexpr (HXREG) {
         using V = typename V16<T>::type;
-        constexpr int NCH = S::N * (int)sizeof(cx<T>) / 16;
+        constexpr int NCH = HX_CH<S, T>;
         sfor<0, HX_IT<S, T>>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             const int c = tid + i * S::THREADS;
@@ -440,7 +444,7 @@ __device__ __forceinline__ void col_load(const CavDesc& d, int cb, ColRegs<S, T,
 }
 
 // TWS / ltw: twiddle source; HXREG / lhx: the propagator table comes from the
-// task registers through the LDS buffer lhx (N entries).
+// task registers through the LDS buffer lhx (HXN entries, index |p~|).
 template <class S, typename T, int MODE, int PROP, int TWS = TW_GLOBAL, bool HXREG = false, class Prefetch>
 __device__ __forceinline__ void col_body(const CavDesc& d, int cb, cx<T>* lds, ColRegs<S, T, HXREG>& in,
                                          Prefetch&& prefetch, const cx<T>* ltw = nullptr, cx<T>* lhx = nullptr) {
@@ -455,7 +459,7 @@ __device__ __forceinline__ void col_body(const CavDesc& d, int cb, cx<T>* lds, C
 
     commit_cols<S, T>(in.q, lds, tid);
     if constexpr (HXREG) {
-        constexpr int NCH = S::N * (int)sizeof(cx<T>) / 16;
+        constexpr int NCH = HX_CH<S, T>;
         sfor<0, HX_IT<S, T>>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             const int c = tid + i * S::THREADS;
@@ -506,11 +510,13 @@ __device__ __forceinline__ void col_body(const CavDesc& d, int cb, cx<T>* lds, C
                 });
             });
         } else if constexpr (HXREG) {
-            const cx<T> hk = lhx[kx];
+            const cx<T> hk = lhx[px < 0 ? -px : px];
             sfor<0, B>([&](auto bc) {
                 sfor<0, RL>([&](auto rc) {
                     constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
-                    v[b * RL + r] = cmul(v[b * RL + r], cmul(hk, lhx[reg_pos<S, RL>(lane, b, r)]));
+                    const int p = reg_pos<S, RL>(lane, b, r);
+                    const int ap = p <= S::N / 2 ? p : S::N - p;
+                    v[b * RL + r] = cmul(v[b * RL + r], cmul(hk, lhx[ap]));
                 });
             });
         } else {
