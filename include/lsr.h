@@ -246,9 +246,12 @@ int lsr_propagator_table(int N, double dx, double lambda, double L, float* out);
 
 /* The Stockham twiddle tables of grid size N (forward then inverse passes,
  * concatenated; per pass with sub-length Ns > 1 and radix R, Ns*R entries
- * w[k*R + r] = exp(-+2 pi i r k/(Ns R))), as interleaved floats built in FP64
- * (prec FP64TAB) or in FP32 arithmetic (PLAIN).  Returns the number of
- * complex entries, or the required count if out is NULL. */
+ * w(k, r) = exp(-+2 pi i r k/(Ns R)), k < Ns, r < R), as interleaved floats
+ * built in FP64 (prec FP64TAB) or in FP32 arithmetic (PLAIN).  Layout inside
+ * a segment, for the lanes of a wave to read contiguous memory: for even R,
+ * w(k, r) sits at (r/2)*2*Ns + 2k + r%2 (the pair r, r+1 of one k adjacent);
+ * for odd R at r*Ns + k.  Returns the number of complex entries, or the
+ * required count if out is NULL. */
 int lsr_twiddle_table(int N, int prec, float* out, int capacity);
 
 /* The batch packer's task order for a set of grid sizes, host only:

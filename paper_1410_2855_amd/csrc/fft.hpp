@@ -119,31 +119,34 @@ __device__ __forceinline__ void line_sync() {
     }
 }
 
-// Load the R twiddles of sub-transform k of a pass whose table segment
-// starts at entry SEG (16-byte vector loads; R even or R == 3).
-template <int R, int SEG, typename T>
+// Load the R twiddles of sub-transform k of a pass (sub-length NS) whose
+// table segment starts at entry SEG, in the tw_index layout: FP32 pairs with
+// one 16-byte load per two twiddles, else one load per twiddle; either way
+// the lanes of a wave (consecutive k) read contiguous memory.
+template <int R, int NS, int SEG, typename T>
 __device__ __forceinline__ void load_tw(cx<T>* w, const cx<T>* __restrict__ tw, int k) {
     constexpr int E = (int)sizeof(cx<T>);
-    const unsigned off = (unsigned)k * (unsigned)(R * E);
     if constexpr (E == 8 && (R % 2 == 0)) {
+        const unsigned off = (unsigned)k * 16u;
         sfor<0, R / 2>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            const float4 q = gld<float4, SEG * E + 16 * i>(tw, off);
+            static_assert(tw_index(NS, R, 0, 2 * i, true) == 2 * i * NS, "pair layout");
+            const float4 q = gld<float4, (SEG + 2 * i * NS) * E>(tw, off);
             w[2 * i] = {(T)q.x, (T)q.y};
             w[2 * i + 1] = {(T)q.z, (T)q.w};
         });
     } else {
+        const unsigned off = (unsigned)k * (unsigned)E;
         sfor<0, R>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            w[i] = gld<cx<T>, SEG * E + E * i>(tw, off);
+            w[i] = gld<cx<T>, (SEG + tw_index(NS, R, 0, i, false)) * E>(tw, off);
         });
     }
 }
 
-// Where the Stockham twiddles come from: TW_GLOBAL reads the plan's table in
-// HBM (k-major, 16-byte loads per lane); TW_LDS reads a copy held in LDS in
-// r-major order (entry r*Ns + k of a segment), so the lanes of a wave read
-// consecutive entries.  Kernels that keep global loads in flight across the
+// Where the Stockham twiddles come from: TW_GLOBAL reads the plan's table
+// (tw_index layout); TW_LDS reads a copy held in LDS in r-major order (entry
+// r*Ns + k of a segment), so the lanes of a wave read consecutive entries.  Kernels that keep global loads in flight across the
 // FFT use TW_LDS: on this ISA waiting for a later global load also waits for
 // every earlier one.
 enum : int { TW_GLOBAL = 0, TW_LDS = 1 };
@@ -167,7 +170,7 @@ __device__ __forceinline__ void pass_compute(cx<T>* v, int lane, const cx<T>* __
                     w[r] = tw[S::tw_off(DIR, PASS) + r * Ns + k];
                 });
             } else {
-                load_tw<R, S::tw_off(DIR, PASS)>(w, tw, k);
+                load_tw<R, Ns, S::tw_off(DIR, PASS)>(w, tw, k);
             }
             sfor<1, R>([&](auto rc) {
                 constexpr int r = decltype(rc)::value;
@@ -178,7 +181,7 @@ __device__ __forceinline__ void pass_compute(cx<T>* v, int lane, const cx<T>* __
     });
 }
 
-// Copy a twiddle table from HBM (k-major segments) into LDS (r-major).
+// Copy a twiddle table from HBM (tw_index layout) into LDS (r-major).
 template <class S, typename T>
 __device__ __forceinline__ void twiddles_to_lds(const cx<T>* __restrict__ tw, cx<T>* ltw, int tid) {
     sfor<0, 2 * S::NP>([&](auto pc) {
@@ -189,8 +192,9 @@ __device__ __forceinline__ void twiddles_to_lds(const cx<T>* __restrict__ tw, cx
         constexpr int off = S::tw_off(dir, pass);
         if constexpr (Ns > 1) {
             for (int i = tid; i < Ns * R; i += S::THREADS) {
-                const int k = i / R, r = i % R;
-                ltw[off + r * Ns + k] = gld<cx<T>>(tw, (unsigned)(sizeof(cx<T>) * (off + i)));
+                const int k = i % Ns, r = i / Ns;
+                const int src = tw_index(Ns, R, k, r, sizeof(T) == 4);
+                ltw[off + r * Ns + k] = gld<cx<T>>(tw, (unsigned)(sizeof(cx<T>) * (off + src)));
             }
         }
     });

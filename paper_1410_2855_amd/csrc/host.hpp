@@ -35,7 +35,8 @@ struct DeviceGuard {
 };
 
 // FP64 (or FP32-emulating) table builders; pure host arithmetic.
-std::vector<double> build_twiddles(const ShapeInfo& s, bool fp32_arith);   // interleaved re, im
+// interleaved re, im; pairs: layout of complex FP32 tables (tw_index)
+std::vector<double> build_twiddles(const ShapeInfo& s, bool fp32_arith, bool pairs);
 std::vector<double> build_hx(int N, double dx, double lambda, double L);   // interleaved, 1/N folded
 std::vector<double> build_pump_cos(int N, double dx, double period);
 std::vector<double> build_focal(int N, double dx, double lambda, double F); // interleaved

@@ -29,13 +29,15 @@ static int sidx(int q, int n) { return (2 * q < n) ? q : q - n; }
 // R and sub-length Ns > 1: entry k*R + r = exp(dir 2 pi i r k / (Ns R)).
 // The angle's integer part r*k < Ns*R is exact, so no further reduction is
 // needed; fp32_arith evaluates the angle and cos/sin in single precision.
-std::vector<double> build_twiddles(const ShapeInfo& s, bool fp32_arith) {
+std::vector<double> build_twiddles(const ShapeInfo& s, bool fp32_arith, bool pairs) {
     std::vector<double> out;
     for (int dir : {FWD, INV}) {
         int ns = 1;
         for (int p = 0; p < s.NP; ++p) {
             const int R = (dir == FWD) ? s.rad[p] : s.rad[s.NP - 1 - p];
             if (ns > 1) {
+                const size_t seg = out.size();
+                out.resize(seg + 2 * (size_t)ns * R);
                 for (int k = 0; k < ns; ++k)
                     for (int r = 0; r < R; ++r) {
                         const long m = (long)r * k;
@@ -50,8 +52,9 @@ std::vector<double> build_twiddles(const ShapeInfo& s, bool fp32_arith) {
                             c = cos(th);
                             sn = sin(th);
                         }
-                        out.push_back(c);
-                        out.push_back(dir * sn);
+                        const size_t at = seg + 2 * (size_t)tw_index(ns, R, k, r, pairs);
+                        out[at] = c;
+                        out[at + 1] = dir * sn;
                     }
             }
             ns *= R;
@@ -211,7 +214,7 @@ int lsr_twiddle_table(int N, int prec, float* out, int capacity) {
     ShapeInfo s;
     if (prec < 0 || prec > 2) return set_err(LSR_EINVAL, "prec %d out of range", prec);
     if (!shape_for(N, prec == PREC_FP64, &s)) return set_err(LSR_EUNSUPPORTED, "N=%d not compiled in", N);
-    std::vector<double> t = build_twiddles(s, prec == PREC_PLAIN);
+    std::vector<double> t = build_twiddles(s, prec == PREC_PLAIN, true);
     const int n = (int)(t.size() / 2);
     if (!out) return n;
     if (capacity < n) return set_err(LSR_EINVAL, "capacity %d < %d twiddles", capacity, n);
@@ -267,7 +270,7 @@ int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L, do
         delete p;
         return code;
     };
-    if ((rc = upload(&p->d_tw, build_twiddles(p->shape, prec == LSR_PREC_PLAIN), f32))) return fail(rc);
+    if ((rc = upload(&p->d_tw, build_twiddles(p->shape, prec == LSR_PREC_PLAIN, prec != LSR_PREC_FP64), f32))) return fail(rc);
     if (prec != LSR_PREC_PLAIN)
         if ((rc = upload(&p->d_hx, build_hx(N, dx, lambda, L), f32))) return fail(rc);
     const bool curved = F != 0.0 && std::isfinite(F);

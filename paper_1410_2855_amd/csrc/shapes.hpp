@@ -50,7 +50,7 @@ struct Shape {
         for (int i = 0; i < NP; ++i) p *= rad_fwd(i);
         return p;
     }
-    // twiddle-table segment of pass s: Ns*R entries (k*R + r) when Ns > 1
+    // twiddle-table segment of pass s: Ns*R entries (see tw_index) when Ns > 1
     static constexpr int tw_len(int dir, int s) { return ns(dir, s) > 1 ? ns(dir, s) * rad(dir, s) : 0; }
     static constexpr int tw_off(int dir, int s) {
         int o = 0;
@@ -79,6 +79,16 @@ struct Shape {
         return true;
     }
 };
+
+// Position of twiddle w^(r k) (sub-transform k < Ns, r < R) inside its pass's
+// segment.  Lanes of a wave hold consecutive k, so the table is laid out for
+// contiguous loads across lanes: with pairs (complex FP32 entries, R even) the
+// two twiddles r, r+1 of one k are adjacent and consecutive k follow, so one
+// 16-byte load per lane reads a pair and a wave reads 1 KB contiguous;
+// otherwise (complex FP64) the table is r-major, entry r*Ns + k.
+constexpr int tw_index(int Ns, int R, int k, int r, bool pairs) {
+    return (pairs && R % 2 == 0) ? (r / 2) * 2 * Ns + 2 * k + (r % 2) : r * Ns + k;
+}
 
 // ---------------------------------------------------------------------------
 // The compiled shapes.  FP32 complex field (8 B/point):

@@ -96,10 +96,13 @@ def test_twiddle_tables(N):
         ns = 1
         for R in order:
             if ns > 1:
+                seg = [0j] * (ns * R)
                 for k in range(ns):
                     for r in range(R):
                         th = 2 * math.pi * r * k / (ns * R)
-                        want.append(complex(math.cos(th), sign * math.sin(th)))
+                        at = (r // 2) * 2 * ns + 2 * k + r % 2 if R % 2 == 0 else r * ns + k
+                        seg[at] = complex(math.cos(th), sign * math.sin(th))
+                want.extend(seg)
             ns *= R
     want = np.asarray(want)
     assert tab.size == want.size == plain.size
