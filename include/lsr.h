@@ -197,10 +197,13 @@ int lsr_batch_set_graph_trips(lsr_batch b, int k);
  * register-budget variant of the kernels (0 = 2 waves/SIMD, 1 = 3).
  * wgs_per_cu: resident workgroups per CU of the persistent kernel (0 =
  * occupancy limit).  chunk: tickets taken per queue access.  lag: packer lag
- * in row tasks.  graph_k: trips per captured graph (0 = eager).  cfg_out
- * (nullable) receives the resulting six values in this order. */
+ * in row tasks.  graph_k: trips per captured graph (0 = eager).  merge:
+ * 0 = one kernel per grid size (each specialised for its size), 1 = cavities
+ * of uneven grid sizes with the same workgroup size share one kernel (one
+ * persistent launch per trip covers them all).  cfg_out (nullable) receives
+ * the resulting seven values in this order. */
 int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, int chunk,
-                        int lag, int graph_k, int* cfg_out);
+                        int lag, int graph_k, int merge, int* cfg_out);
 
 /* Profiling form of lsr_batch_roundtrips (eager, no graph): each pass is
  * launched with HIP events that the dispatch itself timestamps at kernel

@@ -80,6 +80,8 @@ struct Tune {
     int chunk = 2;
     int lag = -1;         // -1 = default
     int graph_k = 16;     // trips per captured graph; 0 = eager
+    int merge = 0;        // 0 one group (kernel) per grid size; 1 one group per
+                          // workgroup size, uneven sizes sharing one kernel
 };
 
 // --------------------------------------------------------------- cache ----
@@ -123,6 +125,7 @@ static std::map<std::string, Tune> cache_read(const std::string& path) {
         get("chunk", t.chunk);
         get("lag", t.lag);
         get("graph_k", t.graph_k);
+        get("merge", t.merge);
         m[key] = t;
         i = cb + 1;
     }
@@ -139,9 +142,9 @@ static bool cache_write(const std::string& path, const std::map<std::string, Tun
     for (const auto& kv : m) {
         fprintf(f,
                 "  \"%s\": {\"engine\": %d, \"variant\": %d, \"wgs_per_cu\": %d, \"chunk\": %d, \"lag\": %d, "
-                "\"graph_k\": %d}%s\n",
+                "\"graph_k\": %d, \"merge\": %d}%s\n",
                 kv.first.c_str(), kv.second.engine, kv.second.variant, kv.second.wgs_per_cu, kv.second.chunk,
-                kv.second.lag, kv.second.graph_k, ++n < m.size() ? "," : "");
+                kv.second.lag, kv.second.graph_k, kv.second.merge, ++n < m.size() ? "," : "");
     }
     fprintf(f, "}\n");
     fclose(f);
@@ -182,8 +185,7 @@ struct lsr_batch_s {
     int graph_trips = 0;
 };
 
-static void batch_free(lsr_batch_s* b) {
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+static void groups_free(lsr_batch_s* b) {
     for (auto& g : b->grp) {
         if (g.d_desc) (void)hipFree(g.d_desc);
         if (g.d_tasks) (void)hipFree(g.d_tasks);
@@ -191,6 +193,14 @@ static void batch_free(lsr_batch_s* b) {
         if (g.d_cols) (void)hipFree(g.d_cols);
         if (g.d_ctrl) (void)hipFree(g.d_ctrl);
     }
+    b->grp.clear();
+    b->lastE.clear();
+    b->lastN.clear();
+}
+
+static void batch_free(lsr_batch_s* b) {
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    groups_free(b);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->stream) (void)hipStreamDestroy(b->stream);
@@ -231,6 +241,57 @@ static int batch_pack(lsr_batch_s* b) {
         g.ncols = (int)cols.size();
     }
     return LSR_OK;
+}
+
+// Cavities -> groups.  merge = 0: one group per grid size (each kernel
+// specialised for its size: registers and LDS of that size only); merge = 1:
+// one group per workgroup size, the smallest compiled kernel that covers all
+// the part's sizes (uneven sizes advance in one launch).  Allocates the
+// groups' descriptor and control blocks and packs their task lists.
+static int batch_partition(lsr_batch_s* b) {
+    groups_free(b);
+    std::map<int, std::vector<int>> parts;
+    for (int i = 0; i < (int)b->plans.size(); ++i) {
+        ShapeInfo s;
+        shape_for(b->plans[i]->N, false, &s);
+        parts[b->tune.merge ? s.threads : b->plans[i]->N].push_back(i);
+    }
+    for (auto& kv : parts) {
+        const GroupInfo* best = nullptr;
+        for (int gi = 0; gi < group_count() && !best; ++gi) {
+            const GroupInfo* g = group_at(gi);
+            if (b->tune.merge ? g->threads != kv.first : (g->nsizes != 1 || g->sizes[0] != kv.first)) continue;
+            bool all = true;
+            for (int c : kv.second) {
+                bool in = false;
+                for (int k = 0; k < g->nsizes; ++k) in |= g->sizes[k] == b->plans[c]->N;
+                all &= in;
+            }
+            if (all) best = g;
+        }
+        if (!best) return set_err(LSR_EUNSUPPORTED, "no compiled group covers this mix of sizes");
+        BatchGroup bg;
+        bg.g = best;
+        bg.cav = kv.second;
+        for (int v = 0; v < best->nvariants; ++v) {
+            bg.occ[v] = best->var[v].occupancy();
+            if (best->var[v].occupancy_pipe) {
+                bg.occ_pipe[v][TASK_ROW] = best->var[v].occupancy_pipe(TASK_ROW);
+                bg.occ_pipe[v][TASK_COL] = best->var[v].occupancy_pipe(TASK_COL);
+            }
+        }
+        const size_t ncav = bg.cav.size();
+        b->grp.push_back(bg);
+        BatchGroup& g = b->grp.back();
+        if (hipMalloc(&g.d_desc, ncav * sizeof(CavDesc)) != hipSuccess ||
+            hipMalloc(&g.d_ctrl, (CTRL_ROWDONE + ncav) * sizeof(unsigned)) != hipSuccess)
+            return set_err(LSR_ENOMEM, "batch allocation failed");
+        std::vector<unsigned> ctrl(CTRL_ROWDONE + ncav, 0u);
+        ctrl[CTRL_NCAV] = (unsigned)ncav;
+        if (hipMemcpy(g.d_ctrl, ctrl.data(), ctrl.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
+            return set_err(LSR_EDEVICE, "control block upload failed");
+    }
+    return batch_pack(b);
 }
 
 static int variant_of(const lsr_batch_s* b, const BatchGroup& g) {
@@ -413,54 +474,11 @@ int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count) {
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)
         return fail(set_err(LSR_EDEVICE, "stream/event creation failed"));
-    // partition by workgroup size, pick the smallest compiled group per part
-    std::map<int, std::vector<int>> parts;
-    for (int i = 0; i < count; ++i) {
-        ShapeInfo s;
-        shape_for(plans[i]->N, false, &s);
-        parts[s.threads].push_back(i);
-    }
-    for (auto& kv : parts) {
-        const GroupInfo* best = nullptr;
-        for (int gi = 0; gi < group_count() && !best; ++gi) {
-            const GroupInfo* g = group_at(gi);
-            if (g->threads != kv.first) continue;
-            bool all = true;
-            for (int c : kv.second) {
-                bool in = false;
-                for (int k = 0; k < g->nsizes; ++k) in |= g->sizes[k] == plans[c]->N;
-                all &= in;
-            }
-            if (all) best = g;
-        }
-        if (!best) return fail(set_err(LSR_EUNSUPPORTED, "no compiled group covers this mix of sizes"));
-        BatchGroup bg;
-        bg.g = best;
-        bg.cav = kv.second;
-        for (int v = 0; v < best->nvariants; ++v) {
-            bg.occ[v] = best->var[v].occupancy();
-            if (best->var[v].occupancy_pipe) {
-                bg.occ_pipe[v][TASK_ROW] = best->var[v].occupancy_pipe(TASK_ROW);
-                bg.occ_pipe[v][TASK_COL] = best->var[v].occupancy_pipe(TASK_COL);
-            }
-        }
-        const size_t ncav = bg.cav.size();
-        if (hipMalloc(&bg.d_desc, ncav * sizeof(CavDesc)) != hipSuccess ||
-            hipMalloc(&bg.d_ctrl, (CTRL_ROWDONE + ncav) * sizeof(unsigned)) != hipSuccess) {
-            b->grp.push_back(bg);
-            return fail(set_err(LSR_ENOMEM, "batch allocation failed"));
-        }
-        std::vector<unsigned> ctrl(CTRL_ROWDONE + ncav, 0u);
-        ctrl[CTRL_NCAV] = (unsigned)ncav;
-        b->grp.push_back(bg);
-        if (hipMemcpy(bg.d_ctrl, ctrl.data(), ctrl.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
-            return fail(set_err(LSR_EDEVICE, "control block upload failed"));
-    }
     b->key = batch_key(b->plans);
     auto cache = cache_read(cache_path(nullptr));
     auto it = cache.find(b->key);
     if (it != cache.end()) b->tune = it->second;
-    int rc = batch_pack(b);
+    const int rc = batch_partition(b);
     if (rc) return fail(rc);
     *out = b;
     return LSR_OK;
@@ -477,9 +495,9 @@ int lsr_batch_set_graph_trips(lsr_batch b, int k) {
 }
 
 int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, int chunk, int lag, int graph_k,
-                        int* cfg_out) {
+                        int merge, int* cfg_out) {
     if (!b) return set_err(LSR_EINVAL, "batch is NULL");
-    if (engine > 2 || variant > 3 || chunk == 0 || chunk > 1024)
+    if (engine > 2 || variant > 3 || chunk == 0 || chunk > 1024 || merge > 1)
         return set_err(LSR_EINVAL, "bad batch configuration");
     DeviceGuard dg(b->device);
     Tune t = b->tune;
@@ -489,12 +507,14 @@ int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, in
     if (chunk > 0) t.chunk = chunk;
     if (lag >= 0) t.lag = lag;
     if (graph_k >= 0) t.graph_k = graph_k;
+    if (merge >= 0) t.merge = merge;
+    const bool regroup = t.merge != b->tune.merge;
     const bool repack = t.lag != b->tune.lag;
     drop_graph(b);
     b->tune = t;
-    if (repack) {
+    if (regroup || repack) {
         LSR_HIP(hipStreamSynchronize(b->stream));
-        const int rc = batch_pack(b);
+        const int rc = regroup ? batch_partition(b) : batch_pack(b);
         if (rc) return rc;
     }
     if (cfg_out) {
@@ -504,6 +524,7 @@ int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, in
         cfg_out[3] = t.chunk;
         cfg_out[4] = t.lag >= 0 ? t.lag : default_lag();
         cfg_out[5] = t.graph_k;
+        cfg_out[6] = t.merge;
     }
     return LSR_OK;
 }
@@ -607,7 +628,8 @@ void lsr_batch_destroy(lsr_batch b) {
 // state; returns ms per trip or a negative status.
 static double time_batch(lsr_batch_s* b, const std::vector<void*>& E, const std::vector<void*>& N, int trips) {
     if (upload_descs(b, E.data(), N.data(), false)) return -1;
-    if (run_trips(b, 2)) return -1;   // warm-up (also builds the graph)
+    // warm-up; with graphs long enough to build the graph outside the timing
+    if (run_trips(b, b->tune.graph_k > 0 ? b->tune.graph_k + 2 : 2)) return -1;
     hipEvent_t t0, t1;
     if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return -1;
     (void)hipEventRecord(t0, b->stream);
@@ -653,52 +675,75 @@ int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
     long pts_total = 0;
     for (auto* q : b->plans) pts_total += (long)q->N * q->N;
     const int trips = pts_total > 32L * 1024 * 1024 ? 6 : 24;
-    int nvar = 1;
-    for (auto& g : b->grp) nvar = std::max(nvar, g.g->nvariants);
-    // grouped launches, plain and software-pipelined: the register budget
-    // is the only other choice
-    for (int eng : {2, 1})
-        for (int v = 0; v < nvar; ++v) {
-            b->tune.engine = eng;
-            b->tune.variant = v;
-            b->tune.graph_k = 16;
-            drop_graph(b);
-            if (batch_pack(b)) continue;
-            const double ms = time_batch(b, E, N, trips);
-            if (ms > 0 && ms < best_ms) {
-                best_ms = ms;
-                best = b->tune;
-            }
+    // merged grouping is a distinct choice only when some workgroup size
+    // holds several grid sizes
+    std::map<int, std::map<int, int>> by_threads;
+    for (auto* q : b->plans) {
+        ShapeInfo sh;
+        shape_for(q->N, false, &sh);
+        by_threads[sh.threads][q->N]++;
+    }
+    bool mixed = false;
+    for (auto& kv : by_threads) mixed |= kv.second.size() > 1;
+    auto consider = [&](const Tune& t, int n) {
+        b->tune = t;
+        drop_graph(b);
+        if (batch_pack(b)) return;
+        const double ms = time_batch(b, E, N, n);
+        if (ms > 0 && ms < best_ms) {
+            best_ms = ms;
+            best = b->tune;
         }
-    for (int v = 0; v < nvar; ++v) {
-        int occ = 1;
-        for (auto& g : b->grp) occ = std::max(occ, g.occ[v < g.g->nvariants ? v : 0]);
-        std::vector<int> wgs;
-        for (int w = occ; w >= 1 && (int)wgs.size() < 3; --w) wgs.push_back(w);
-        for (int w : wgs)
-            for (int chunk : {1, 2, 4, 8})
-                for (int lag : {512, 2048, 8192}) {
-                b->tune.engine = 0;
-                b->tune.variant = v;
-                b->tune.wgs_per_cu = w;
-                b->tune.chunk = chunk;
-                b->tune.lag = lag;
-                b->tune.graph_k = 16;
-                drop_graph(b);
-                if (batch_pack(b)) continue;
-                const double ms = time_batch(b, E, N, trips);
-                if (ms > 0 && ms < best_ms) {
-                    best_ms = ms;
-                    best = b->tune;
-                }
-                }
+    };
+    for (int mg = 0; mg <= (mixed ? 1 : 0); ++mg) {
+        b->tune = saved;
+        b->tune.merge = mg;
+        if (batch_partition(b)) continue;
+        const Tune base = b->tune;
+        int nvar = 1;
+        for (auto& g : b->grp) nvar = std::max(nvar, g.g->nvariants);
+        // grouped launches, plain and software-pipelined: the register budget
+        // is the only other choice
+        for (int eng : {2, 1})
+            for (int v = 0; v < nvar; ++v) {
+                Tune t = base;
+                t.engine = eng;
+                t.variant = v;
+                t.graph_k = 16;
+                consider(t, trips);
+            }
+        for (int v = 0; v < nvar; ++v) {
+            int occ = 1;
+            for (auto& g : b->grp) occ = std::max(occ, g.occ[v < g.g->nvariants ? v : 0]);
+            std::vector<int> wgs;
+            for (int w = occ; w >= 1 && (int)wgs.size() < 3; --w) wgs.push_back(w);
+            for (int w : wgs)
+                for (int chunk : {1, 2, 4, 8})
+                    for (int lag : {512, 2048, 8192}) {
+                        Tune t = base;
+                        t.engine = 0;
+                        t.variant = v;
+                        t.wgs_per_cu = w;
+                        t.chunk = chunk;
+                        t.lag = lag;
+                        t.graph_k = 16;
+                        consider(t, trips);
+                    }
+        }
+    }
+    if (best.merge != b->tune.merge) {
+        b->tune = best;
+        if (batch_partition(b)) {
+            release();
+            return set_err(LSR_EDEVICE, "autotune: regrouping failed");
+        }
     }
     for (int k : {0, 4, 16, 64}) {
         b->tune = best;
         b->tune.graph_k = k;
         drop_graph(b);
         if (batch_pack(b)) continue;
-        const double ms = time_batch(b, E, N, std::max(trips, k + 1));
+        const double ms = time_batch(b, E, N, std::max(trips, k));
         if (ms > 0 && ms < best_ms * 0.995) {
             best_ms = ms;
             best = b->tune;

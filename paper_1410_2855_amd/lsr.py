@@ -62,7 +62,7 @@ _SIGS = {
     "lsr_batch_roundtrips": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i]),
     "lsr_batch_diag": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(lsr_diag_out)]),
     "lsr_batch_set_graph_trips": (_i, [_vp, _i]),
-    "lsr_batch_configure": (_i, [_vp, _i, _i, _i, _i, _i, _i, ctypes.POINTER(_i)]),
+    "lsr_batch_configure": (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, ctypes.POINTER(_i)]),
     "lsr_batch_time_kernels": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, ctypes.POINTER(_d)]),
     "lsr_batch_destroy": (None, [_vp]),
     "lsr_autotune": (_i, [_vp, _vp, ctypes.c_char_p]),
@@ -245,10 +245,11 @@ def lsr_batch_set_graph_trips(batch, k: int):
     _check(load().lsr_batch_set_graph_trips(batch, k))
 
 
-def lsr_batch_configure(batch, engine=-1, variant=-1, wgs_per_cu=-1, chunk=-1, lag=-1, graph_k=-1) -> dict:
-    out = (ctypes.c_int * 6)()
-    _check(load().lsr_batch_configure(batch, engine, variant, wgs_per_cu, chunk, lag, graph_k, out))
-    return dict(zip(("engine", "variant", "wgs_per_cu", "chunk", "lag", "graph_k"), out[:]))
+def lsr_batch_configure(batch, engine=-1, variant=-1, wgs_per_cu=-1, chunk=-1, lag=-1, graph_k=-1,
+                        merge=-1) -> dict:
+    out = (ctypes.c_int * 7)()
+    _check(load().lsr_batch_configure(batch, engine, variant, wgs_per_cu, chunk, lag, graph_k, merge, out))
+    return dict(zip(("engine", "variant", "wgs_per_cu", "chunk", "lag", "graph_k", "merge"), out[:]))
 
 
 def lsr_batch_time_kernels(batch, Es, Ns, n_trips: int):

@@ -48,24 +48,28 @@ def mixed(count, sizes):
     return cavs
 
 
-@pytest.mark.parametrize("sizes,count,trips,k,engine", [
-    ((256, 384, 512, 768, 1024), 9, 13, 4, 2),  # mixed group, graph + remainder
-    ((256, 384, 512, 768, 1024), 5, 6, 2, 0),   # mixed group, persistent kernel
-    ((1024,), 5, 7, 0, 2),                       # single-size group, pipelined, eager
-    ((1024,), 5, 7, 3, 1),                       # grouped, not pipelined
-    ((1024,), 4, 5, 2, 0),                       # persistent kernel
-    ((1024,), 3, 1, 16, 2),                      # one trip: FIRST + LAST only
-    ((2048,), 2, 5, 2, 2),
-    ((256, 2048), 4, 6, 3, 2),                   # 256..2048 group
-    ((4096, 512), 2, 3, 1, 2),                   # two workgroup sizes: two groups
-    ((384,), 7, 4, 2, 2),
+@pytest.mark.parametrize("sizes,count,trips,k,engine,merge", [
+    ((256, 384, 512, 768, 1024), 9, 13, 4, 2, 1),  # one kernel for all sizes, graph + remainder
+    ((256, 384, 512, 768, 1024), 9, 13, 4, 1, 0),  # one kernel per size
+    ((256, 384, 512, 768, 1024), 5, 6, 2, 0, 1),   # one persistent kernel for all sizes
+    ((256, 384, 512, 768, 1024), 5, 6, 2, 0, 0),   # a persistent kernel per size
+    ((1024,), 5, 7, 0, 2, 0),                      # single-size group, pipelined, eager
+    ((1024,), 5, 7, 3, 1, 0),                      # grouped, not pipelined
+    ((1024,), 4, 5, 2, 0, 0),                      # persistent kernel
+    ((1024,), 3, 1, 16, 2, 0),                     # one trip: FIRST + LAST only
+    ((2048,), 2, 5, 2, 2, 0),
+    ((256, 2048), 4, 6, 3, 2, 1),                  # 256..2048 kernel
+    ((256, 2048), 4, 6, 3, 1, 0),
+    ((4096, 512), 2, 3, 1, 2, 1),                  # two workgroup sizes: two groups either way
+    ((384,), 7, 4, 2, 2, 0),
 ])
-def test_batch_is_bitwise_the_plain_path(sizes, count, trips, k, engine):
+def test_batch_is_bitwise_the_plain_path(sizes, count, trips, k, engine, merge):
     cavs = mixed(count, sizes)
     ref, ref_tr = plain_reference(cavs, trips)
     plans, Es, Ns = make(cavs)
     b = lsr.lsr_batch_create([p.handle for p in plans])
-    lsr.lsr_batch_configure(b, engine=engine)
+    cfg = lsr.lsr_batch_configure(b, engine=engine, merge=merge)
+    assert cfg["engine"] == engine and cfg["merge"] == merge
     lsr.lsr_batch_set_graph_trips(b, k)
     lsr.lsr_batch_roundtrips(b, Es, Ns, trips)
     for p in plans:
@@ -140,6 +144,27 @@ def test_autotune_writes_cache_and_keeps_results(tmp_path):
     lsr.lsr_autotune(None, b, path)
     text = open(path).read()
     assert "gfx950:batch:512x3;" in text
+    lsr.lsr_batch_roundtrips(b, Es, Ns, 9)
+    ref, _ = plain_reference(cavs, 9)
+    for i in range(len(cavs)):
+        assert torch.equal(Es[i], ref[i][0]) and torch.equal(Ns[i], ref[i][1])
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
+
+
+def test_autotune_mixed_sizes_keeps_results(tmp_path):
+    """A batch whose grid sizes share a workgroup size: the tuner also times
+    the merged kernel; whatever it picks, the results stay bitwise those of
+    the one-cavity path."""
+    cavs = mixed(4, (256, 512))
+    plans, Es, Ns = make(cavs)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    path = str(tmp_path / "tune.json")
+    lsr.lsr_autotune(None, b, path)
+    assert '"merge"' in open(path).read()
+    cfg = lsr.lsr_batch_configure(b)
+    assert cfg["merge"] in (0, 1)
     lsr.lsr_batch_roundtrips(b, Es, Ns, 9)
     ref, _ = plain_reference(cavs, 9)
     for i in range(len(cavs)):
