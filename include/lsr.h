@@ -250,10 +250,11 @@ int lsr_propagator_table(int N, double dx, double lambda, double L, float* out);
 /* The Stockham twiddle tables of grid size N (forward then inverse passes,
  * concatenated; per pass with sub-length Ns > 1 and radix R, Ns*R entries
  * w(k, r) = exp(-+2 pi i r k/(Ns R)), k < Ns, r < R), as interleaved floats
- * built in FP64 (prec FP64TAB) or in FP32 arithmetic (PLAIN).  Layout inside
- * a segment, for the lanes of a wave to read contiguous memory: for even R,
- * w(k, r) sits at (r/2)*2*Ns + 2k + r%2 (the pair r, r+1 of one k adjacent);
- * for odd R at r*Ns + k.  Returns the number of complex entries, or the
+ * built in FP64 (prec FP64TAB and FP64; the FP64 shape's passes for FP64) or
+ * in FP32 arithmetic (PLAIN), returned rounded to float.  Layout inside a
+ * segment, for the lanes of a wave to read contiguous memory: for the FP32
+ * forms and even R, w(k, r) sits at (r/2)*2*Ns + 2k + r%2 (the pair r, r+1
+ * of one k adjacent); for odd R, and for FP64, at r*Ns + k.  Returns the number of complex entries, or the
  * required count if out is NULL. */
 int lsr_twiddle_table(int N, int prec, float* out, int capacity);
 

@@ -22,12 +22,11 @@ GroupInfo group_1024();
 GroupInfo group_2048();
 GroupInfo group_4096();
 GroupInfo group_small();
-GroupInfo group_all256();
 
 static const std::vector<GroupInfo>& groups() {
     static const std::vector<GroupInfo> g = {group_256(),  group_384(),  group_512(),
                                              group_768(),  group_1024(), group_2048(),
-                                             group_4096(), group_small(), group_all256()};
+                                             group_4096(), group_small()};
     return g;
 }
 int group_count() { return (int)groups().size(); }

@@ -214,7 +214,7 @@ int lsr_twiddle_table(int N, int prec, float* out, int capacity) {
     ShapeInfo s;
     if (prec < 0 || prec > 2) return set_err(LSR_EINVAL, "prec %d out of range", prec);
     if (!shape_for(N, prec == PREC_FP64, &s)) return set_err(LSR_EUNSUPPORTED, "N=%d not compiled in", N);
-    std::vector<double> t = build_twiddles(s, prec == PREC_PLAIN, true);
+    std::vector<double> t = build_twiddles(s, prec == PREC_PLAIN, prec != PREC_FP64);
     const int n = (int)(t.size() / 2);
     if (!out) return n;
     if (capacity < n) return set_err(LSR_EINVAL, "capacity %d < %d twiddles", capacity, n);

@@ -93,11 +93,11 @@ constexpr int tw_index(int Ns, int R, int k, int r, bool pairs) {
 // ---------------------------------------------------------------------------
 // The compiled shapes.  FP32 complex field (8 B/point):
 using S256  = Shape<256, 16, 16, 16, 16>;
-using S384  = Shape<384, 16, 16, 8, 12, 4>;
+using S384  = Shape<384, 32, 8, 12, 4, 4, 2>;
 using S512  = Shape<512, 32, 8, 8, 8, 8>;
-using S768  = Shape<768, 32, 8, 8, 12, 8>;
+using S768  = Shape<768, 64, 4, 12, 4, 4, 4>;
 using S1024 = Shape<1024, 64, 4, 4, 16, 16>;
-using S2048 = Shape<2048, 64, 4, 8, 16, 16>;
+using S2048 = Shape<2048, 128, 4, 8, 16, 16>;
 using S4096 = Shape<4096, 256, 4, 16, 16, 16>;
 // FP64 complex field (16 B/point): half the lines per workgroup.
 using D256  = Shape<256, 16, 8, 16, 16>;

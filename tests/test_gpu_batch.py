@@ -58,7 +58,7 @@ def mixed(count, sizes):
     ((1024,), 4, 5, 2, 0, 0),                      # persistent kernel
     ((1024,), 3, 1, 16, 2, 0),                     # one trip: FIRST + LAST only
     ((2048,), 2, 5, 2, 2, 0),
-    ((256, 2048), 4, 6, 3, 2, 1),                  # 256..2048 kernel
+    ((256, 2048), 4, 6, 3, 2, 1),                  # different workgroup sizes: two kernels
     ((256, 2048), 4, 6, 3, 1, 0),
     ((4096, 512), 2, 3, 1, 2, 1),                  # two workgroup sizes: two groups either way
     ((384,), 7, 4, 2, 2, 0),
