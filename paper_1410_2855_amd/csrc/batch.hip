@@ -673,7 +673,7 @@ int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
     double best_ms = 1e30;
     long pts_total = 0;
     for (auto* q : b->plans) pts_total += (long)q->N * q->N;
-    const int trips = pts_total > 32L * 1024 * 1024 ? 6 : 24;
+    const int trips = pts_total > 32L * 1024 * 1024 ? 20 : 40;
     // merged grouping is a distinct choice only when some workgroup size
     // holds several grid sizes
     std::map<int, std::map<int, int>> by_threads;
