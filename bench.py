@@ -149,9 +149,26 @@ def summarize(out_dir: str, workload: str, cavities: int, grid: int):
     print(json.dumps(traffic, indent=1))
 
 
+WORKLOADS = {
+    "sweep1024": "%d cavities at 1024^2 (sweep parameter draws), FP64-table form",
+    "sweep512": "512 cavities, N uniform in {256, 384, 512, 768, 1024} (sweep draws), FP64-table form",
+    "structured4096": "16 cavities at 4096^2, F=1000, periodic pump (M = 45..89 periods), FP64-table form",
+}
+
+
+def make_workload(name: str, cavities: int):
+    from paper_1410_2855_amd.inputs import structured_4096, sweep, sweep_1024
+
+    if name == "sweep1024":
+        return sweep_1024(cavities), WORKLOADS[name] % cavities
+    if name == "sweep512":
+        return sweep(512), WORKLOADS[name]
+    return structured_4096(16), WORKLOADS[name]
+
+
 def cpu_baseline(cav, seconds_target: float = 12.0):
-    """The FP64 oracle, single-threaded, on one 1024^2 cavity of the workload:
-    as many round trips as fit in about seconds_target."""
+    """The FP64 oracle, single-threaded, on the workload's first cavity: as
+    many round trips as fit in about seconds_target."""
     import oracle
     from paper_1410_2855_amd.inputs import initial_state, oracle_params
 
@@ -166,7 +183,7 @@ def cpu_baseline(cav, seconds_target: float = 12.0):
     dt = time.perf_counter() - t0
     return {"value": cav.N * cav.N * trips / dt, "unit": "grid-pts*round-trips/s", "cores": 1,
             "kind": "oracle",
-            "sample": "%d round trips of one 1024^2 cavity of the workload (FP64 C, one thread)" % trips}
+            "sample": "%d round trips of the workload's first cavity, %d^2 (FP64 C, one thread)" % (trips, cav.N)}
 
 
 def main():
@@ -174,7 +191,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cavities", type=int, default=64)
+    ap.add_argument("--cavities", type=int, default=64, help="cavities of the 1024^2 workload")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="sweep1024",
+                    help="sweep1024 (default, the metric's configuration): 1024^2 cavities with the sweep's "
+                         "parameter draws; sweep512: 512 cavities of N in {256..1024}; structured4096: "
+                         "16 cavities at 4096^2 with the periodic pump")
     ap.add_argument("--autotune", action="store_true", help="retune the batch and update the cache")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
@@ -198,13 +219,13 @@ def main():
     import torch
 
     from paper_1410_2855_amd import lsr
-    from paper_1410_2855_amd.inputs import initial_state, sweep_1024
+    from paper_1410_2855_amd.inputs import initial_state
 
     lsr.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    cavs = sweep_1024(args.cavities)
+    cavs, workload = make_workload(args.workload, args.cavities)
     plans, Es, Ns = [], [], []
     for c in cavs:
         p = lsr.Plan(c, prec=lsr.LSR_PREC_FP64TAB, stream=stream)
@@ -267,7 +288,8 @@ def main():
                 "event_trip_ms": round(trip_ms, 5)}
 
     out = {
-        "metric": "grid-pts x round-trips/s at 1024^2 (batched vs plain)",
+        "metric": "grid-pts x round-trips/s at 1024^2 (batched vs plain)" if args.workload == "sweep1024"
+                  else "grid-pts x round-trips/s (batched vs plain)",
         "value": value,
         "unit": "grid-pts*round-trips/s",
         "n_gpus": 1,
@@ -279,8 +301,8 @@ def main():
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": "%d cavities at 1024^2 (sweep parameter draws), FP64-table form" % len(cavs),
-                   "grid": 1024, "cavities": len(cavs), "mode": "batched",
+        "config": {"workload": workload,
+                   "grid": sorted({c.N for c in cavs}), "cavities": len(cavs), "mode": "batched",
                    "engine": "grouped" if cfg["engine"] == 1 else "persistent", "launch": cfg},
         "plain": {"value": plain_value, "ms_per_step": t_plain * 1e3},
         "speedup_batched_vs_plain": value / plain_value,

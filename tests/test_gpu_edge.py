@@ -1,0 +1,144 @@
+"""Degenerate and boundary cases of the round-trip map on the GPU.
+
+Each case reduces the map to something with a plain answer (no diffraction,
+no field, a lossless mirror, full relaxation) or exercises a boundary of the
+implementation (a one-cavity batch, every grid size in one batch, the trace
+ring wrapping around).
+"""
+import dataclasses
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1410_2855_amd.inputs import Cavity, initial_state, oracle_params, sweep
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1410_2855_amd import lsr  # noqa: E402
+
+TAB = lsr.LSR_PREC_FP64TAB
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def test_zero_length_is_the_local_map_alone():
+    """L = 0: the propagator is the identity (every phase is zero), so the
+    round trip is the local step alone; GPU and oracle agree, and the field
+    equals sqrt(R) A exp(N/2) E point by point after one trip."""
+    cav = Cavity(N=512, F=200.0, R=0.9, pump_ratio=2.0, T1=800.0, index=4)
+    h = lsr.lsr_plan_create(cav.N, cav.dx, cav.lam, 0.0, 0.0, cav.R, ap_kind=cav.ap_kind,
+                            ap_radius=cav.ap_radius, ap_order=cav.ap_order, prec=TAB)
+    lsr.lsr_plan_set_gain(h, cav.N0, cav.T1)
+    e0, n0 = initial_state(cav)
+    e = torch.from_numpy(e0).to("cuda", torch.complex64)
+    n = torch.from_numpy(n0).to("cuda", torch.float32)
+    lsr.lsr_roundtrips(h, e, n, 1)
+    lsr.lsr_sync(h)
+    x = (np.arange(cav.N) - cav.N / 2) * cav.dx
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    A = np.exp(-((X ** 2 + Y ** 2) / cav.ap_radius ** 2) ** 5)
+    want = np.sqrt(cav.R) * A * np.exp(n0 / 2) * e0
+    assert rel(e.cpu().numpy(), want) <= 1e-6
+    lsr.lsr_roundtrips(h, e, n, 9)
+    lsr.lsr_sync(h)
+    lsr.lsr_plan_destroy(h)
+    p = dataclasses.replace(oracle_params(cav), L=0.0)
+    eo, no, _ = oracle.run(p, e0, n0, 10)
+    assert rel(e.cpu().numpy(), eo) <= 1e-5 and rel(n.cpu().numpy(), no) <= 1e-5
+
+
+def test_zero_field_stays_zero_and_inversion_relaxes():
+    """E = 0 is a fixed point of the field; the inversion then relaxes by the
+    linear recursion N <- N + (N0 - N)/T1, so N_k - N0 = (N_init - N0)(1 - 1/T1)^k."""
+    cav = Cavity(N=256, F=100.0, R=0.9, pump_ratio=2.0, T1=50.0, index=0)
+    p = lsr.Plan(cav)
+    n_init = np.random.default_rng(3).uniform(0.0, 0.5, (cav.N, cav.N))
+    e, n = p.state(np.zeros((cav.N, cav.N), np.complex128), n_init)
+    k = 40
+    p.roundtrips(e, n, k)
+    p.sync()
+    assert torch.count_nonzero(e).item() == 0
+    want = cav.N0 + (n_init - cav.N0) * (1 - 1 / cav.T1) ** k
+    assert np.max(np.abs(n.cpu().numpy() - want)) <= 1e-5
+    p.close()
+
+
+def test_lossless_mirror_and_full_relaxation():
+    """R = 1 and T1 = 1 (the inversion returns to the pump every trip, minus
+    the depletion) against the oracle."""
+    cav = Cavity(N=384, F=150.0, R=1.0, pump_ratio=2.0, T1=1.0, index=9, n0_override=0.3)
+    e0, n0 = initial_state(cav)
+    p = lsr.Plan(cav)
+    e, n = p.state(e0, n0)
+    p.roundtrips(e, n, 20)
+    p.sync()
+    p.close()
+    eo, no, _ = oracle.run(oracle_params(cav), e0, n0, 20)
+    assert rel(e.cpu().numpy(), eo) <= 1e-5 and rel(n.cpu().numpy(), no) <= 1e-5
+
+
+def _batch_vs_plain(cavs, trips, engine):
+    refs = []
+    for c in cavs:
+        p = lsr.Plan(c)
+        e, n = p.state(*initial_state(c))
+        p.roundtrips(e, n, trips)
+        p.sync()
+        refs.append((e, n))
+        p.close()
+    plans, Es, Ns = [], [], []
+    for c in cavs:
+        p = lsr.Plan(c)
+        e, n = p.state(*initial_state(c))
+        plans.append(p)
+        Es.append(e)
+        Ns.append(n)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_configure(b, engine=engine)
+    lsr.lsr_batch_roundtrips(b, Es, Ns, trips)
+    for p in plans:
+        p.sync()
+    for i in range(len(cavs)):
+        assert torch.equal(Es[i], refs[i][0]) and torch.equal(Ns[i], refs[i][1]), "cavity %d" % i
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
+
+
+def test_batch_of_one_cavity():
+    _batch_vs_plain(sweep(1, seed=5, sizes=(512,)), 4, 1)
+
+
+@pytest.mark.parametrize("engine", [1, 0])
+def test_batch_with_every_grid_size(engine):
+    """One cavity of each compiled size, 256 .. 4096, in one batch."""
+    cavs = [c.with_(N=N, index=i) for i, (c, N) in
+            enumerate(zip(sweep(7, seed=6), (256, 384, 512, 768, 1024, 2048, 4096)))]
+    _batch_vs_plain(cavs, 3, engine)
+
+
+def test_trace_ring_wraps_and_keeps_the_latest_trips():
+    """With a 16-record trace ring, 40 trips leave the last 16 records."""
+    cav = Cavity(N=256, F=100.0, R=0.9, pump_ratio=2.0, T1=1000.0, index=1)
+    os.environ["LSR_TRACE_CAP"] = "16"
+    try:
+        p = lsr.Plan(cav)
+    finally:
+        del os.environ["LSR_TRACE_CAP"]
+    e0, n0 = initial_state(cav)
+    e, n = p.state(e0, n0)
+    p.roundtrips(e, n, 40)
+    p.sync()
+    tr = p.trace(64)
+    p.close()
+    assert tr.shape == (16, 4)
+    _, _, to = oracle.run(oracle_params(cav), e0, n0, 40)
+    assert rel(tr, to[-16:]) <= 1e-5
