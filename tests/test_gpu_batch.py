@@ -62,6 +62,10 @@ def mixed(count, sizes):
     ((256, 2048), 4, 6, 3, 1, 0),
     ((4096, 512), 2, 3, 1, 2, 1),                  # two workgroup sizes: two groups either way
     ((384,), 7, 4, 2, 2, 0),
+    ((1024,), 9, 7, 3, 3, 0),                      # persistent kernel, one queue per XCD
+    ((256, 384, 512, 768, 1024), 11, 6, 2, 3, 1),  # one XCD-local kernel for all sizes
+    ((256, 384, 512, 768, 1024), 11, 6, 0, 3, 0),  # XCD-local kernels per size, eager
+    ((4096, 512), 2, 3, 1, 3, 1),
 ])
 def test_batch_is_bitwise_the_plain_path(sizes, count, trips, k, engine, merge):
     cavs = mixed(count, sizes)
