@@ -193,10 +193,7 @@ int lsr_batch_set_graph_trips(lsr_batch b, int k);
  * (every cavity's row blocks, then every cavity's column blocks), 2 = grouped
  * launches whose resident workgroups prefetch their next task's data while
  * computing the current one (groups of a single grid size; other groups fall
- * back to 1), 3 = one persistent kernel per round trip with one task queue per
- * XCD: each cavity's tasks all run on one XCD (one L2), so a column task
- * needs no device-wide cache write-back or invalidation to see its row
- * tasks' results.  variant:
+ * back to 1).  variant:
  * register-budget variant of the kernels (0 = 2 waves/SIMD, 1 = 3).
  * wgs_per_cu: resident workgroups per CU of the persistent kernel (0 =
  * occupancy limit).  chunk: tickets taken per queue access.  lag: packer lag

@@ -6,7 +6,6 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -32,43 +31,6 @@ static const std::vector<GroupInfo>& groups() {
 }
 int group_count() { return (int)groups().size(); }
 const GroupInfo* group_at(int i) { return (i >= 0 && i < group_count()) ? &groups()[i] : nullptr; }
-
-// Which XCC ids (XCDs, each with its own L2) the device runs workgroups on:
-// one probe launch per device, cached.  map[id] = queue index (~0u if the id
-// never appeared); returns the number of queues (0 on failure).
-__global__ void k_xcc_probe(unsigned* seen) {
-    unsigned v;
-    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
-    if (threadIdx.x == 0) atomicOr(seen, 1u << (v & 15u));
-}
-
-static int xcc_queues(int device, unsigned* map) {
-    static std::mutex mu;
-    static std::map<int, unsigned> masks;
-    unsigned mask = 0;
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = masks.find(device);
-        if (it != masks.end()) {
-            mask = it->second;
-        } else {
-            unsigned* d = nullptr;
-            if (hipMalloc(&d, sizeof(unsigned)) != hipSuccess) return 0;
-            bool ok = hipMemset(d, 0, sizeof(unsigned)) == hipSuccess;
-            if (ok) {
-                hipLaunchKernelGGL(k_xcc_probe, dim3(4096), dim3(64), 0, 0, d);
-                ok = hipGetLastError() == hipSuccess &&
-                     hipMemcpy(&mask, d, sizeof(unsigned), hipMemcpyDeviceToHost) == hipSuccess;
-            }
-            (void)hipFree(d);
-            if (!ok || !mask) return 0;
-            masks[device] = mask;
-        }
-    }
-    int nq = 0;
-    for (int i = 0; i < MAX_QUEUES; ++i) map[i] = (mask >> i) & 1u ? (unsigned)nq++ : ~0u;
-    return nq;
-}
 
 int row_blocks(int N) {
     ShapeInfo s;
@@ -111,8 +73,7 @@ static int default_lag() { return 2048; }
 
 struct Tune {
     int engine = 1;       // 0 persistent kernel per trip, 1 grouped launch per pass,
-                          // 2 grouped and software-pipelined (single-size groups),
-                          // 3 persistent kernel with one task queue per XCD
+                          // 2 grouped and software-pipelined (single-size groups)
     int variant = 0;      // kernel variant (register budget) of each group
     int wgs_per_cu = 0;   // 0 = occupancy limit
     int chunk = 2;
@@ -203,8 +164,6 @@ struct BatchGroup {
     int nlast = 0;
     int4* d_cols = nullptr;          // column tasks only (grouped column pass)
     int ncols = 0;
-    int4* d_xtasks = nullptr;        // per-XCD queues of trip tasks, concatenated
-    int nxtasks = 0;
     unsigned* d_ctrl = nullptr;
     int occ[4] = {1, 1, 1, 1};   // resident workgroups per CU of each variant
     int occ_pipe[4][2] = {};     // same for the pipelined row / column pass
@@ -231,7 +190,6 @@ static void groups_free(lsr_batch_s* b) {
         if (g.d_tasks) (void)hipFree(g.d_tasks);
         if (g.d_last) (void)hipFree(g.d_last);
         if (g.d_cols) (void)hipFree(g.d_cols);
-        if (g.d_xtasks) (void)hipFree(g.d_xtasks);
         if (g.d_ctrl) (void)hipFree(g.d_ctrl);
     }
     b->grp.clear();
@@ -280,50 +238,6 @@ static int batch_pack(lsr_batch_s* b) {
         g.ntasks = (int)t.size();
         g.nlast = (int)l.size();
         g.ncols = (int)cols.size();
-        // XCD-local queues: cavities to queues by longest-processing-time
-        // (work ~ N^2), each queue packed like the single queue
-        unsigned xmap[MAX_QUEUES];
-        const int nq = xcc_queues(b->device, xmap);
-        if (g.d_xtasks) (void)hipFree(g.d_xtasks);
-        g.d_xtasks = nullptr;
-        g.nxtasks = 0;
-        if (nq > 0) {
-            std::vector<int> order(g.cav.size());
-            for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-            std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
-                return b->plans[g.cav[a]]->N > b->plans[g.cav[c]]->N;
-            });
-            std::vector<std::vector<int>> qc(nq);
-            std::vector<long> load(nq, 0);
-            for (int i : order) {
-                const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-                qc[q].push_back(i);
-                load[q] += (long)b->plans[g.cav[i]]->N * b->plans[g.cav[i]]->N;
-            }
-            std::vector<int4> x;
-            std::vector<unsigned> info(2 * MAX_QUEUES, 0u);
-            for (int q = 0; q < nq; ++q) {
-                std::vector<int> qn;
-                for (int i : qc[q]) qn.push_back(nrb[i]);
-                std::vector<int4> tq;
-                pack(qn, lag, true, tq);
-                info[2 * q] = (unsigned)x.size();
-                info[2 * q + 1] = (unsigned)tq.size();
-                for (int4 e : tq) {
-                    e.x = qc[q][e.x];
-                    x.push_back(e);
-                }
-            }
-            if (hipMalloc(&g.d_xtasks, x.size() * sizeof(int4)) != hipSuccess)
-                return set_err(LSR_ENOMEM, "task table allocation failed");
-            LSR_HIP(hipMemcpy(g.d_xtasks, x.data(), x.size() * sizeof(int4), hipMemcpyHostToDevice));
-            g.nxtasks = (int)x.size();
-            const unsigned nqw = (unsigned)nq;
-            LSR_HIP(hipMemcpy(g.d_ctrl + CTRL_NQ, &nqw, sizeof(unsigned), hipMemcpyHostToDevice));
-            LSR_HIP(hipMemcpy(g.d_ctrl + CTRL_XMAP, xmap, sizeof xmap, hipMemcpyHostToDevice));
-            LSR_HIP(hipMemcpy(g.d_ctrl + CTRL_QINFO, info.data(), info.size() * sizeof(unsigned),
-                              hipMemcpyHostToDevice));
-        }
     }
     return LSR_OK;
 }
@@ -416,7 +330,7 @@ static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind, LaunchEvents 
 }
 
 static int launch_trip(lsr_batch_s* b, int mode, LaunchEvents ev = {}) {
-    if (b->tune.engine == 1 || b->tune.engine == 2) {
+    if (b->tune.engine >= 1) {
         // grouped: every cavity's row blocks, then every cavity's column blocks
         int rc = launch_grouped_pass(b, mode, TASK_ROW);
         if (rc == LSR_OK && mode != ROW_LAST) rc = launch_grouped_pass(b, mode, TASK_COL);
@@ -426,23 +340,13 @@ static int launch_trip(lsr_batch_s* b, int mode, LaunchEvents ev = {}) {
     for (size_t i = 0; i < ng; ++i) {
         auto& g = b->grp[i];
         const bool last = mode == ROW_LAST;
+        const int nt = last ? g.nlast : g.ntasks;
+        const int grid = std::min(grid_of(b, g), nt);
         LaunchEvents e;
         if (i == 0) e.start = ev.start;
         if (i + 1 == ng) e.stop = ev.stop;
-        const KernelVariant& kv = g.g->var[variant_of(b, g)];
-        int rc;
-        if (b->tune.engine == 3) {
-            if (!g.d_xtasks) return set_err(LSR_EUNSUPPORTED, "XCD-local engine: no XCD queues on this device");
-            // one workgroup per CU at least, so every XCD serves its queue
-            rc = kv.launch_x(mode, std::max(grid_of(b, g), b->cus), b->stream, g.d_desc, g.d_xtasks, g.d_ctrl,
-                             last ? 1 : b->tune.chunk, e);
-        } else {
-            const int nt = last ? g.nlast : g.ntasks;
-            const int grid = std::min(grid_of(b, g), nt);
-            rc = kv.launch(mode, grid, b->stream, g.d_desc, last ? g.d_last : g.d_tasks, nt, g.d_ctrl,
-                           last ? 1 : b->tune.chunk, e);
-        }
-        if (rc)
+        if (g.g->var[variant_of(b, g)].launch(mode, grid, b->stream, g.d_desc, last ? g.d_last : g.d_tasks, nt,
+                                              g.d_ctrl, last ? 1 : b->tune.chunk, e))
             return set_err(LSR_EDEVICE, "persistent kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     }
     return LSR_OK;
@@ -592,7 +496,7 @@ int lsr_batch_set_graph_trips(lsr_batch b, int k) {
 int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, int chunk, int lag, int graph_k,
                         int merge, int* cfg_out) {
     if (!b) return set_err(LSR_EINVAL, "batch is NULL");
-    if (engine > 3 || variant > 3 || chunk == 0 || chunk > 1024 || merge > 1)
+    if (engine > 2 || variant > 3 || chunk == 0 || chunk > 1024 || merge > 1)
         return set_err(LSR_EINVAL, "bad batch configuration");
     DeviceGuard dg(b->device);
     Tune t = b->tune;
@@ -666,7 +570,7 @@ int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* N, int n_tr
                 if (x) (void)hipEventDestroy(x);
             return set_err(LSR_EDEVICE, "hipEventCreate failed");
         }
-    const bool grouped = b->tune.engine == 1 || b->tune.engine == 2;
+    const bool grouped = b->tune.engine >= 1;
     for (int t = 0; t <= n_trips && rc == LSR_OK; ++t) {
         const int mode = t == 0 ? ROW_FIRST : (t == n_trips ? ROW_LAST : ROW_MID);
         if (grouped) {
@@ -817,19 +721,6 @@ int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
                     for (int lag : {512, 2048, 8192}) {
                         Tune t = base;
                         t.engine = 0;
-                        t.variant = v;
-                        t.wgs_per_cu = w;
-                        t.chunk = chunk;
-                        t.lag = lag;
-                        t.graph_k = 16;
-                        consider(t, trips);
-                    }
-            // XCD-local persistent kernel
-            for (int w : wgs)
-                for (int chunk : {2, 4})
-                    for (int lag : {1024, 4096, 16384}) {
-                        Tune t = base;
-                        t.engine = 3;
                         t.variant = v;
                         t.wgs_per_cu = w;
                         t.chunk = chunk;

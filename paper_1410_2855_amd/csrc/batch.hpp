@@ -9,16 +9,8 @@ namespace lsr {
 
 enum : int { TASK_ROW = 0, TASK_COL = 1 };
 
-// Control block of a group (device, unsigned words).  The XCD-local engine
-// keeps one task queue per XCD: CTRL_XMAP maps the hardware XCC id to a queue
-// (~0u = none), CTRL_QINFO holds (first task, task count) per queue and each
-// queue's ticket head sits at CTRL_QHEAD + 32 q.
-enum : int { MAX_QUEUES = 16 };
-enum : int {
-    CTRL_HEAD = 0, CTRL_EXIT = 1, CTRL_NCAV = 2, CTRL_ABORT = 3, CTRL_NQ = 4,
-    CTRL_XMAP = 16, CTRL_QINFO = 32, CTRL_QHEAD = 64,
-    CTRL_ROWDONE = CTRL_QHEAD + 32 * MAX_QUEUES
-};
+// Control block of a group (device, unsigned words).
+enum : int { CTRL_HEAD = 0, CTRL_EXIT = 1, CTRL_NCAV = 2, CTRL_ABORT = 3, CTRL_ROWDONE = 16 };
 
 // Optional timestamps of one dispatch: when either event is set the launch
 // goes through hipExtLaunchKernelGGL, which records the kernel's own start
@@ -39,9 +31,6 @@ struct KernelVariant {
     // software-pipelined grouped pass (single-size groups only; else null)
     int (*launch_pipe)(int mode, int kind, hipStream_t st, const CavDesc* descs, const int4* tasks, int ntasks,
                        int grid, LaunchEvents ev);
-    // persistent kernel with one task queue per XCD (queues in the control block)
-    int (*launch_x)(int mode, int grid, hipStream_t st, const CavDesc* descs, const int4* tasks, unsigned* ctrl,
-                    int chunk, LaunchEvents ev);
     int (*occupancy_pipe)(int kind);
 };
 

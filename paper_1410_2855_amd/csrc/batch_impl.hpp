@@ -25,6 +25,11 @@
 
 namespace lsr {
 
+// Reset a queue counter with an atomic read-modify-write (returns the old value).
+__device__ __forceinline__ unsigned atomic_zero(unsigned* p) {
+    return __hip_atomic_exchange(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Sizes sharing one persistent kernel: same workgroup size; the LDS buffer
 // is the largest of their line buffers.
 template <class S0, class... Ss>
@@ -81,7 +86,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
                         if (__hip_atomic_load(ctrl + CTRL_ABORT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
                         __builtin_amdgcn_s_sleep(2);
                         if (++spins > (1u << 25)) {   // ~2 s
-                            __hip_atomic_store(ctrl + CTRL_ABORT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            (void)__hip_atomic_exchange(ctrl + CTRL_ABORT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             d.counters[CNT_HANG] = 1u;
                             break;
                         }
@@ -108,107 +113,12 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
     if (threadIdx.x == 0) {
         const unsigned old = __hip_atomic_fetch_add(ctrl + CTRL_EXIT, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (old == gridDim.x - 1) {
+            // counters change only by atomic read-modify-writes, resets included
             const int ncav = (int)ctrl[CTRL_NCAV];
-            for (int c = 0; c < ncav; ++c) done[c] = 0u;
-            ctrl[CTRL_HEAD] = 0u;
-            ctrl[CTRL_ABORT] = 0u;
-            ctrl[CTRL_EXIT] = 0u;
-        }
-    }
-}
-
-// Hardware id of the XCD (accelerator complex die) running this wave.  Each
-// XCD has its own L2 cache.
-__device__ __forceinline__ unsigned xcc_id() {
-    unsigned v;
-    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
-    return v & 15u;
-}
-
-// XCD-local persistent round trip.  The host assigns every cavity to one
-// queue per XCD; a workgroup serves only the queue of the XCD it runs on, so
-// all tasks of a cavity run under one L2.  Inside a launch each tile line is
-// written by exactly one row task and then read and written by exactly one
-// column task, so the only ordering needed is that a row task's stores have
-// reached the shared L2 before its row-done count is published (wait for the
-// stores, then the count), and that a column task starts after the count is
-// complete: no L2 write-back or invalidation as a device-wide release and
-// acquire would need.  Waits are bounded as in k_trip; a queue that no
-// workgroup served (an XCD without workgroups) is reported through the
-// cavities' failure counters instead of being left undone silently.
-template <int MODE, int THREADS, int LDS_BYTES, int WPE, class... Ss>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_tripx(
-    const CavDesc* __restrict__ descs, const int4* __restrict__ tasks, unsigned* __restrict__ ctrl, int chunk) {
-    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
-    __shared__ double red[4 * 16];
-    __shared__ int s_ticket;
-    unsigned* done = ctrl + CTRL_ROWDONE;
-    const unsigned q = ctrl[CTRL_XMAP + xcc_id()];
-    if (q < (unsigned)MAX_QUEUES) {
-        unsigned* head = ctrl + CTRL_QHEAD + 32 * q;
-        const int first = (int)ctrl[CTRL_QINFO + 2 * q];
-        const int ntasks = (int)ctrl[CTRL_QINFO + 2 * q + 1];
-        for (;;) {
-            if (threadIdx.x == 0)
-                s_ticket = (int)__hip_atomic_fetch_add(head, (unsigned)chunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __syncthreads();
-            const int t0 = __builtin_amdgcn_readfirstlane(s_ticket);
-            if (t0 >= ntasks) break;
-            const int t1 = t0 + chunk < ntasks ? t0 + chunk : ntasks;
-            for (int t = t0; t < t1; ++t) {
-                const int4 tk = tasks[first + t];
-                const int cav = __builtin_amdgcn_readfirstlane(tk.x);
-                const int kind = __builtin_amdgcn_readfirstlane(tk.y);
-                const int blk = __builtin_amdgcn_readfirstlane(tk.z);
-                const CavDesc& d = descs[cav];
-                // the last trip of a call is the inverse row transform only
-                if (MODE == ROW_LAST && kind == TASK_COL) continue;
-                if (kind == TASK_COL) {
-                    if (threadIdx.x == 0) {
-                        const unsigned need = (unsigned)d.nrb;
-                        unsigned spins = 0;
-                        while (__hip_atomic_load(done + cav, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                            if (__hip_atomic_load(ctrl + CTRL_ABORT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-                            __builtin_amdgcn_s_sleep(2);
-                            if (++spins > (1u << 25)) {   // ~2 s
-                                __hip_atomic_store(ctrl + CTRL_ABORT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                d.counters[CNT_HANG] = 1u;
-                                break;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                    if (blk == 0 && threadIdx.x < 64) finalize_sums<true>(d);
-                }
-                (run_if<MODE, Ss>(d, kind, blk, smem, red) || ...);
-                if (kind == TASK_ROW) {
-                    // every wave's stores acknowledged by the L2 before the count
-                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-                    __syncthreads();
-                    if (threadIdx.x == 0)
-                        __hip_atomic_fetch_add(done + cav, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                __syncthreads();
-            }
-        }
-    }
-    if (threadIdx.x == 0) {
-        const unsigned old = __hip_atomic_fetch_add(ctrl + CTRL_EXIT, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == gridDim.x - 1) {
-            const int ncav = (int)ctrl[CTRL_NCAV];
-            const int nq = (int)ctrl[CTRL_NQ];
-            bool undone = false;
-            for (int i = 0; i < nq; ++i) {
-                unsigned* h = ctrl + CTRL_QHEAD + 32 * i;
-                undone |= __hip_atomic_load(h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < ctrl[CTRL_QINFO + 2 * i + 1];
-                __hip_atomic_store(h, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            for (int c = 0; c < ncav; ++c) {
-                if (undone) descs[c].counters[CNT_HANG] = 1u;
-                __hip_atomic_store(done + c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            __hip_atomic_store(ctrl + CTRL_ABORT, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(ctrl + CTRL_EXIT, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int c = 0; c < ncav; ++c) atomic_zero(done + c);
+            atomic_zero(ctrl + CTRL_HEAD);
+            atomic_zero(ctrl + CTRL_ABORT);
+            atomic_zero(ctrl + CTRL_EXIT);
         }
     }
 }
@@ -345,17 +255,6 @@ struct GroupKernels {
         }
         return hipGetLastError() == hipSuccess ? 0 : -3;
     }
-    static int launch_x(int mode, int grid, hipStream_t st, const CavDesc* descs, const int4* tasks, unsigned* ctrl,
-                        int chunk, LaunchEvents ev) {
-        const dim3 g(grid), b(THREADS);
-        switch (mode) {
-        case ROW_FIRST: LSR_LAUNCH((k_tripx<ROW_FIRST, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks, ctrl, chunk); break;
-        case ROW_MID:   LSR_LAUNCH((k_tripx<ROW_MID, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks, ctrl, chunk); break;
-        case ROW_LAST:  LSR_LAUNCH((k_tripx<ROW_LAST, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks, ctrl, chunk); break;
-        default: return -1;
-        }
-        return hipGetLastError() == hipSuccess ? 0 : -3;
-    }
     static int occupancy() {
         int n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trip<ROW_MID, THREADS, LDS, WPE, Ss...>, THREADS, 0) != hipSuccess)
@@ -413,7 +312,7 @@ struct GroupKernels {
         }
     }
     static KernelVariant variant() {
-        KernelVariant v{&launch, &launch_pass, &occupancy, WPE, nullptr, &launch_x, nullptr};
+        KernelVariant v{&launch, &launch_pass, &occupancy, WPE, nullptr, nullptr};
         if constexpr (PIPE) {
             v.launch_pipe = &launch_pipe;
             v.occupancy_pipe = &occupancy_pipe;

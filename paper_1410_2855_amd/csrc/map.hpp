@@ -223,21 +223,13 @@ __device__ __forceinline__ void block_sums_store(double* acc, double* red, doubl
 }
 
 // Ordered reduction of a cavity's row-block partials into its trace ring;
-// run by one full wavefront.  Flags the first non-finite trip.  COHERENT
-// reads the partials with device-coherent loads (partials written earlier in
-// the same launch by other compute units).
-template <bool COHERENT = false>
+// run by one full wavefront.  Flags the first non-finite trip.
 __device__ __forceinline__ void finalize_sums(const CavDesc& d) {
     const int lane = threadIdx.x & 63;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int rb = lane; rb < d.nrb; rb += 64) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if constexpr (COHERENT)
-                s[q] += __hip_atomic_load(d.partials + 4 * rb + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            else
-                s[q] += d.partials[4 * rb + q];
-        }
+        for (int q = 0; q < 4; ++q) s[q] += d.partials[4 * rb + q];
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) s[q] = wave_sum(s[q]);
