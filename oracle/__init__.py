@@ -55,6 +55,7 @@ class _Params(ctypes.Structure):
         ("T1", ctypes.c_double),
         ("mod_amp", ctypes.c_double),
         ("mod_period", ctypes.c_double),
+        ("filter_delta", ctypes.c_double),
     ]
 
 
@@ -104,6 +105,7 @@ class CavityParams:
     ap_mask: np.ndarray | None = None
     mod_amp: float = 0.0
     mod_period: float = 0.0
+    filter_delta: float = 0.0   # > 0: Gaussian renormalization-group filter instead of Fresnel
 
     def _c(self):
         p = _Params()
@@ -111,6 +113,7 @@ class CavityParams:
         p.focal = 0.0 if not np.isfinite(self.focal) else self.focal
         p.R, p.ap_kind, p.ap_radius, p.ap_order = self.R, self.ap_kind, self.ap_radius, self.ap_order
         p.N0, p.T1, p.mod_amp, p.mod_period = self.N0, self.T1, self.mod_amp, self.mod_period
+        p.filter_delta = self.filter_delta
         keep = None
         if self.ap_kind == 3:
             keep = np.ascontiguousarray(self.ap_mask, dtype=np.float64).reshape(self.N, self.N)

@@ -219,6 +219,7 @@ static int params_ok(const orc_params* p)
     if ((p->ap_kind == 1 || p->ap_kind == 2) && !(p->ap_radius > 0.0)) return 0;
     if (p->ap_kind == 1 && p->ap_order < 1) return 0;
     if (p->ap_kind == 3 && !p->ap_mask) return 0;
+    if (!(p->filter_delta >= 0.0) || !isfinite(p->filter_delta)) return 0;
     return 1;
 }
 
@@ -291,14 +292,25 @@ int orc_run(const orc_params* p, double* E, double* Ninv, int n_trips,
      * (Sec. 2.3, Eq. (25)): the Laplacian is -4 pi^2 (fx^2 + fy^2) in Fourier
      * space and k = 2 pi / lambda, so H = exp(-i pi lambda L (fx^2 + fy^2)).
      * It is the Fourier transform of the Fresnel kernel of Eqs. (11), (13). */
+    /* With filter_delta > 0 the nonlocal step is instead the real kernel of
+     * the renormalization-group fixed point (Sec. 2.3, Eq. (18)), the
+     * operator exp[(Delta^2/2) d^2/dx^2] applied along both transverse axes:
+     * in Fourier space d^2/dx^2 -> -4 pi^2 fx^2, so
+     * H = exp(-2 pi^2 Delta^2 (fx^2 + fy^2)), real and at most 1. */
     for (int q = 0; q < N; q++)
         for (int pp = 0; pp < N; pp++) {
             double fx = signed_index(pp, N) / (N * p->dx);
             double fy = signed_index(q, N) / (N * p->dx);
-            double ph = M_PI * p->lambda * p->L * (fx * fx + fy * fy);
             size_t i = (size_t)q * N + pp;
-            H[2 * i] = cos(ph);
-            H[2 * i + 1] = -sin(ph);
+            if (p->filter_delta > 0.0) {
+                double d2 = p->filter_delta * p->filter_delta;
+                H[2 * i] = exp(-2.0 * M_PI * M_PI * d2 * (fx * fx + fy * fy));
+                H[2 * i + 1] = 0.0;
+            } else {
+                double ph = M_PI * p->lambda * p->L * (fx * fx + fy * fy);
+                H[2 * i] = cos(ph);
+                H[2 * i + 1] = -sin(ph);
+            }
         }
     const double sqR = sqrt(p->R);
     const double inv_nn = 1.0 / ((double)N * (double)N);

@@ -33,6 +33,10 @@ typedef struct {
     double T1;          /* inversion relaxation time (round trips)            */
     double mod_amp;     /* pump modulation depth (0 = uniform pump)            */
     double mod_period;  /* pump modulation period d (m); 0 = uniform          */
+    double filter_delta;/* > 0: the real renormalization-group filter
+                           exp[(Delta^2/2) Laplacian] (Sec. 2.3, Eq. (18)) of
+                           deviation Delta (m) replaces the Fresnel step;
+                           0 = Fresnel propagation over L                       */
 } orc_params;
 
 /* One-dimensional DFT of length n = 2^a 3^b, in place, unnormalized.

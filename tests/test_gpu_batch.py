@@ -196,3 +196,26 @@ def test_persistent_kernel_with_interleaved_rows_and_columns(chunk, lag):
     lsr.lsr_batch_destroy(b)
     for p in plans:
         p.close()
+
+
+def test_batch_follows_new_state_buffers_between_calls():
+    """The batch keeps per-cavity descriptors (and graphs reading them) on the
+    device; a call with other state tensors must act on those tensors."""
+    cavs = mixed(4, (512, 1024))
+    ref, _ = plain_reference(cavs, 12)
+    plans, Es, Ns = make(cavs)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_set_graph_trips(b, 2)
+    lsr.lsr_batch_roundtrips(b, Es, Ns, 6)
+    Es2 = [e.clone() for e in Es]
+    Ns2 = [n.clone() for n in Ns]
+    keep = [(e.clone(), n.clone()) for e, n in zip(Es, Ns)]
+    lsr.lsr_batch_roundtrips(b, Es2, Ns2, 6)
+    torch.cuda.synchronize()
+    for i in range(len(cavs)):
+        assert torch.equal(Es2[i], ref[i][0]) and torch.equal(Ns2[i], ref[i][1])
+        # the first buffers were left alone by the second call
+        assert torch.equal(Es[i], keep[i][0]) and torch.equal(Ns[i], keep[i][1])
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()

@@ -361,3 +361,49 @@ def test_spectrum_dc_is_excluded_from_the_dominant_bin():
     radial, k = oracle.spectrum(p, e, np.zeros((n, n)))
     assert radial[0] > radial[2]
     assert k == 2
+
+
+# ------------------------------------- renormalization-group filter ----
+
+def test_rg_filter_spreads_a_gaussian_like_the_heat_kernel():
+    """Sec. 2.3, Eq. (18): the universal real kernel exp[(Delta^2/2) d^2/dx^2],
+    applied along both transverse axes, is the heat semigroup at time
+    Delta^2/2: a Gaussian exp(-r^2/a) becomes a/(a + 2 Delta^2) exp(-r^2/(a + 2 Delta^2))."""
+    n, dx = 256, 1e-5
+    a = (12 * dx) ** 2
+    delta = 5 * dx
+    p = passive(n, dx, 1.064e-6, 2e-3, filter_delta=delta)
+    X, Y = grid(n, dx)
+    r2 = X ** 2 + Y ** 2
+    e, _, _ = oracle.run(p, np.exp(-r2 / a), np.zeros((n, n)), 1)
+    b = a + 2 * delta ** 2
+    assert rel(e, a / b * np.exp(-r2 / b)) <= 1e-12
+
+
+def test_rg_filter_eigenmode_and_semigroup():
+    """A plane wave of spatial frequency f is an eigenfunction with eigenvalue
+    exp(-2 pi^2 Delta^2 f^2); two passes with Delta equal one with Delta sqrt(2)."""
+    n, dx = 128, 2e-5
+    delta = 3 * dx
+    X, Y = grid(n, dx)
+    fx, fy = 5 / (n * dx), -3 / (n * dx)
+    wave = np.exp(2j * np.pi * (fx * X + fy * Y))
+    e, _, _ = oracle.run(passive(n, dx, 1.064e-6, 2e-3, filter_delta=delta), wave, np.zeros((n, n)), 1)
+    lam = math.exp(-2 * math.pi ** 2 * delta ** 2 * (fx ** 2 + fy ** 2))
+    assert rel(e, lam * wave) <= 1e-13
+    e0 = rand_c((n, n), 4)
+    e2, _, _ = oracle.run(passive(n, dx, 1.064e-6, 2e-3, filter_delta=delta), e0, np.zeros((n, n)), 2)
+    e1, _, _ = oracle.run(passive(n, dx, 1.064e-6, 2e-3, filter_delta=delta * math.sqrt(2)), e0,
+                          np.zeros((n, n)), 1)
+    assert rel(e2, e1) <= 1e-13
+
+
+def test_rg_filter_never_adds_energy_and_rejects_bad_widths():
+    n, dx = 64, 1e-5
+    e0 = rand_c((n, n), 8)
+    e, _, tr = oracle.run(passive(n, dx, 1.064e-6, 2e-3, filter_delta=2 * dx), e0, np.zeros((n, n)), 5)
+    s = list(tr[:, 0]) + [np.sum(np.abs(e) ** 2)]
+    assert all(b < a for a, b in zip(s, s[1:]))
+    for bad in (-1e-6, float("nan"), float("inf")):
+        with pytest.raises(ValueError):
+            oracle.run(passive(n, dx, 1.064e-6, 2e-3, filter_delta=bad), e0, np.zeros((n, n)), 1)
