@@ -114,9 +114,21 @@ typedef struct {
  * The gain defaults to N0 = 0, T1 = 1 (set it with lsr_plan_set_gain), the
  * stream to the null stream.  Tables are built in FP64 on the host and
  * uploaded once; no allocation happens in later calls except lsr_diag's
- * first use of its spectrum scratch. */
+ * first use of its spectrum scratch and table replacement by
+ * lsr_plan_set_gain / lsr_plan_set_filter. */
 int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L,
                     double F, double R, const lsr_aperture* ap, lsr_prec prec);
+
+/* Nonlocal step of the map: delta > 0 replaces the Fresnel propagation by
+ * the real renormalization-group filter of Sec. 2.3, Eq. (18),
+ * exp[(delta^2/2) d^2/dx^2] applied along both transverse axes, i.e. the
+ * Fourier multiplier exp(-2 pi^2 delta^2 (fx^2 + fy^2)); delta (m) is the
+ * kernel's deviation.  delta = 0 restores the propagator.  The table is built
+ * in FP64, as the propagator's; every precision form takes it from the table.
+ * Waits for the plan's stream (the old table may still be in use) and
+ * allocates the new table; batches holding the plan pick the change up on
+ * their next call.  LSR_EINVAL for delta < 0 or non-finite. */
+int lsr_plan_set_filter(lsr_plan p, double delta);
 
 /* Pump and relaxation (Eq. (1), second line; periodic pump of Sec. 3):
  * N0(x,y) = N0 (1 + mod_amp cos(2 pi x/mod_period) cos(2 pi y/mod_period)),

@@ -178,6 +178,7 @@ struct lsr_batch_s {
     std::vector<lsr_plan> plans;
     std::vector<BatchGroup> grp;
     std::vector<void*> lastE, lastN;
+    std::vector<unsigned> lastVer;   // plan descriptor versions of the last upload
     Tune tune;
     std::string key;
     hipGraphExec_t graph = nullptr;
@@ -384,7 +385,8 @@ static int ensure_graph(lsr_batch_s* b, int k) {
 // Per-cavity descriptors: refreshed when the state pointers change.
 static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool force) {
     bool same = !force && b->lastE.size() == b->plans.size();
-    for (size_t i = 0; same && i < b->plans.size(); ++i) same = b->lastE[i] == E[i] && b->lastN[i] == N[i];
+    for (size_t i = 0; same && i < b->plans.size(); ++i)
+        same = b->lastE[i] == E[i] && b->lastN[i] == N[i] && b->lastVer[i] == b->plans[i]->version;
     if (same) return LSR_OK;
     for (auto& g : b->grp) {
         std::vector<CavDesc> h;
@@ -399,6 +401,8 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
     }
     b->lastE.assign(E, E + b->plans.size());
     b->lastN.assign(N, N + b->plans.size());
+    b->lastVer.clear();
+    for (auto* p : b->plans) b->lastVer.push_back(p->version);
     return LSR_OK;
 }
 

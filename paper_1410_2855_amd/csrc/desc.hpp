@@ -25,7 +25,8 @@ struct CavDesc {
     void* E;                // field (row-major between calls, tiled inside)
     void* Ninv;             // inversion, row-major
     const void* tw;         // Stockham twiddles of this N (forward, then inverse passes)
-    const void* hx;         // per-axis propagator hx(p) (FP64TAB / FP64), N entries
+    const void* hx;         // per-axis factor hx(p) of the nonlocal step, N entries: the
+                            // propagator (FP64TAB / FP64) or the real filter (any form)
     const void* pump_c;     // cos(2 pi x_i / d), N entries, or null (uniform pump)
     const void* foc;        // exp(i pi x_i^2/(lambda F)), N complex entries, or null (flat mirror)
     const void* mask;       // N*N aperture amplitude (AP_MASK) or null
@@ -41,7 +42,7 @@ struct CavDesc {
     int trace_cap;
     int nrb;                // row blocks = column blocks = N / LPW
     int nbins;
-    int pad_;
+    int prop_kind;          // 0 Fresnel propagator (hx), 1 real filter table (hx holds it)
     double sqrtR;
     double N0, inv_T1, mod_amp;
     double dx;

@@ -37,7 +37,8 @@ struct DeviceGuard {
 // FP64 (or FP32-emulating) table builders; pure host arithmetic.
 // interleaved re, im; pairs: layout of complex FP32 tables (tw_index)
 std::vector<double> build_twiddles(const ShapeInfo& s, bool fp32_arith, bool pairs);
-std::vector<double> build_hx(int N, double dx, double lambda, double L);   // interleaved, 1/N folded
+std::vector<double> build_hx(int N, double dx, double lambda, double L);
+std::vector<double> build_filter(int N, double dx, double delta);   // interleaved, 1/N folded
 std::vector<double> build_pump_cos(int N, double dx, double period);
 std::vector<double> build_focal(int N, double dx, double lambda, double F); // interleaved
 
@@ -52,6 +53,8 @@ struct lsr_plan_s {
     double dx = 0, lambda = 0, L = 0, F = 0, R = 1;
     lsr_aperture ap{};
     double N0 = 0, T1 = 1, mod_amp = 0, mod_period = 0;
+    double filter = 0;                 // > 0: width of the real filter replacing the propagator
+    unsigned version = 0;              // bumped whenever the descriptor d changes
     hipStream_t stream = nullptr;
     const lsr::Launchers* kern = nullptr;
     lsr::ShapeInfo shape{};

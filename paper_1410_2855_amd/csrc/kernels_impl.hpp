@@ -43,7 +43,9 @@ int launch_col_t(const CavDesc& d, int mode, hipStream_t st) {
     const dim3 g(S::N / S::LPW), b(S::THREADS);
     switch (mode) {
     case COL_PROP:
-        if (d.prec == PREC_PLAIN) hipLaunchKernelGGL((k_col<S, T, COL_PROP, PROP_PHASE>), g, b, 0, st, d);
+        // the plain form evaluates the Fresnel phase on the device; a filter
+        // (or any FP64-built propagator) comes from the table
+        if (d.prec == PREC_PLAIN && d.prop_kind == 0) hipLaunchKernelGGL((k_col<S, T, COL_PROP, PROP_PHASE>), g, b, 0, st, d);
         else hipLaunchKernelGGL((k_col<S, T, COL_PROP, PROP_TABLE>), g, b, 0, st, d);
         break;
     case COL_DIAG: hipLaunchKernelGGL((k_col<S, T, COL_DIAG, PROP_TABLE>), g, b, 0, st, d); break;

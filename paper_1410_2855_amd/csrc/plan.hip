@@ -79,6 +79,19 @@ std::vector<double> build_hx(int N, double dx, double lambda, double L) {
     return out;
 }
 
+// Real renormalization-group filter of deviation delta (Sec. 2.3, Eq. (18)),
+// exp[(delta^2/2) d^2/dx^2] per axis: hf(p) = exp(-2 pi^2 delta^2 fx_p^2) / N,
+// zero imaginary part; the same separable form and 1/N folding as hx.
+std::vector<double> build_filter(int N, double dx, double delta) {
+    std::vector<double> out(2 * (size_t)N, 0.0);
+    const double W = (double)N * dx;
+    for (int p = 0; p < N; ++p) {
+        const double f = (double)sidx(p, N) / W;
+        out[2 * p] = exp(-0.5 * kTwoPi * kTwoPi * delta * delta * f * f) / N;
+    }
+    return out;
+}
+
 // cos(2 pi x_i / d), x_i = (i - N/2) dx, argument reduced to [0, 1) turns.
 std::vector<double> build_pump_cos(int N, double dx, double period) {
     std::vector<double> out((size_t)N);
@@ -308,6 +321,7 @@ int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L, do
                : a.kind == 2 ? 1.0 / (2.0 * a.radius * a.radius) : 0.0;
     d.phase_c = kTwoPi * 0.5 * lambda * L / ((N * dx) * (N * dx));
     d.inv_nn = 1.0 / ((double)N * (double)N);
+    d.prop_kind = 0;
     *out = p;
     return LSR_OK;
 }
@@ -339,6 +353,32 @@ int lsr_plan_set_gain(lsr_plan p, double N0, double T1, double mod_amp, double m
     p->d.inv_T1 = 1.0 / T1;
     p->d.mod_amp = modulated ? mod_amp : 0.0;
     p->d.pump_c = modulated ? p->d_pump : nullptr;
+    ++p->version;
+    return LSR_OK;
+}
+
+int lsr_plan_set_filter(lsr_plan p, double delta) {
+    if (!p) return set_err(LSR_EINVAL, "plan is NULL");
+    if (!(delta >= 0) || !std::isfinite(delta)) return set_err(LSR_EINVAL, "filter width must be >= 0");
+    DeviceGuard g(p->device);
+    void* t = nullptr;
+    if (delta > 0) {
+        int rc = upload(&t, build_filter(p->N, p->dx, delta), p->prec != PREC_FP64);
+        if (rc) return rc;
+    } else if (p->prec != PREC_PLAIN) {
+        int rc = upload(&t, build_hx(p->N, p->dx, p->lambda, p->L), p->prec != PREC_FP64);
+        if (rc) return rc;
+    }
+    if (p->d_hx) {
+        // the old table may still be read by enqueued work
+        LSR_HIP(hipStreamSynchronize(p->stream));
+        (void)hipFree(p->d_hx);
+    }
+    p->d_hx = t;
+    p->filter = delta;
+    p->d.hx = t;
+    p->d.prop_kind = delta > 0 ? 1 : 0;
+    ++p->version;
     return LSR_OK;
 }
 

@@ -51,6 +51,7 @@ class Cavity:
     mod_amp: float = 0.0
     mod_periods: int = 0     # integer number of pump periods across the window
     n0_override: float | None = None
+    filter_delta: float = 0.0  # > 0: real renormalization-group filter (m) instead of Fresnel
 
     @property
     def a(self) -> float:
@@ -101,7 +102,8 @@ def oracle_params(cav: Cavity):
     return CavityParams(N=cav.N, dx=cav.dx, lam=cav.lam, L=cav.L, R=cav.R,
                         N0=cav.N0, T1=cav.T1, focal=cav.focal, ap_kind=cav.ap_kind,
                         ap_radius=cav.ap_radius, ap_order=cav.ap_order,
-                        mod_amp=cav.mod_amp, mod_period=cav.mod_period)
+                        mod_amp=cav.mod_amp, mod_period=cav.mod_period,
+                        filter_delta=cav.filter_delta)
 
 
 # --------------------------------------------------------------------------

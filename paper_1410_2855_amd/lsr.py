@@ -50,6 +50,7 @@ _d = ctypes.c_double
 _SIGS = {
     "lsr_plan_create": (_i, [ctypes.POINTER(_vp), _i, _d, _d, _d, _d, _d, ctypes.POINTER(lsr_aperture), _i]),
     "lsr_plan_set_gain": (_i, [_vp, _d, _d, _d, _d]),
+    "lsr_plan_set_filter": (_i, [_vp, _d]),
     "lsr_plan_set_stream": (_i, [_vp, _vp]),
     "lsr_roundtrips": (_i, [_vp, _vp, _vp, _i]),
     "lsr_sync": (_i, [_vp]),
@@ -171,6 +172,10 @@ def lsr_plan_set_gain(plan, N0, T1, mod_amp=0.0, mod_period=0.0):
     _check(load().lsr_plan_set_gain(plan, N0, T1, mod_amp, mod_period))
 
 
+def lsr_plan_set_filter(plan, delta: float):
+    _check(load().lsr_plan_set_filter(plan, float(delta)))
+
+
 def lsr_plan_set_stream(plan, stream):
     _check(load().lsr_plan_set_stream(plan, _stream_handle(stream)))
 
@@ -285,6 +290,8 @@ class Plan:
                                       ap_kind=cav.ap_kind, ap_radius=cav.ap_radius,
                                       ap_order=cav.ap_order, prec=prec)
         lsr_plan_set_gain(self.handle, cav.N0, cav.T1, cav.mod_amp, cav.mod_period)
+        if getattr(cav, "filter_delta", 0.0):
+            lsr_plan_set_filter(self.handle, cav.filter_delta)
         lsr_plan_set_stream(self.handle, stream if stream is not None else torch.cuda.current_stream())
 
     @property
