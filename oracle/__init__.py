@@ -56,6 +56,7 @@ class _Params(ctypes.Structure):
         ("mod_amp", ctypes.c_double),
         ("mod_period", ctypes.c_double),
         ("filter_delta", ctypes.c_double),
+        ("model", ctypes.c_int),
     ]
 
 
@@ -106,6 +107,7 @@ class CavityParams:
     mod_amp: float = 0.0
     mod_period: float = 0.0
     filter_delta: float = 0.0   # > 0: Gaussian renormalization-group filter instead of Fresnel
+    model: int = 0              # 0 B class (Euler), 1 B class (exact over a trip), 2 class A
 
     def _c(self):
         p = _Params()
@@ -114,6 +116,7 @@ class CavityParams:
         p.R, p.ap_kind, p.ap_radius, p.ap_order = self.R, self.ap_kind, self.ap_radius, self.ap_order
         p.N0, p.T1, p.mod_amp, p.mod_period = self.N0, self.T1, self.mod_amp, self.mod_period
         p.filter_delta = self.filter_delta
+        p.model = self.model
         keep = None
         if self.ap_kind == 3:
             keep = np.ascontiguousarray(self.ap_mask, dtype=np.float64).reshape(self.N, self.N)

@@ -220,6 +220,7 @@ static int params_ok(const orc_params* p)
     if (p->ap_kind == 1 && p->ap_order < 1) return 0;
     if (p->ap_kind == 3 && !p->ap_mask) return 0;
     if (!(p->filter_delta >= 0.0) || !isfinite(p->filter_delta)) return 0;
+    if (p->model < 0 || p->model > 2) return 0;
     return 1;
 }
 
@@ -268,6 +269,37 @@ static double pump(const orc_params* p, int y, int x)
     double cx = cos(2.0 * M_PI * coord(x, p) / p->mod_period);
     double cy = cos(2.0 * M_PI * coord(y, p) / p->mod_period);
     return p->N0 * (1.0 + p->mod_amp * cx * cy);
+}
+
+/* Amplitude factor of the gain sheet for inversion Nn and incident
+ * intensity I.  B-class (models 0, 1): the inversion is frozen during the
+ * pass (Intro), amplitude gain exp(N/2).  Class A (model 2, Sec. 2.1,
+ * Eq. (8)): the gain term sigma N / (2 (1 + sigma T1 |E|^2)) integrated over
+ * one round trip with |E|^2 frozen, i.e. amplitude gain
+ * exp(N / (2 (1 + T1 I))). */
+static double gain_amp(const orc_params* p, double Nn, double I)
+{
+    if (p->model == 2) return exp(0.5 * Nn / (1.0 + p->T1 * I));
+    return exp(0.5 * Nn);
+}
+
+/* Inversion after one round trip, from Nn, the local pump level P and the
+ * incident intensity I (sigma = 1, time in round trips).
+ * Model 0: forward Euler of dN/dt = (P - N)/T1 - N I, the reading of the
+ *          second line of Eq. (1).
+ * Model 1: the same equation (Eq. (6)) solved exactly over one trip with I
+ *          frozen: N relaxes to N_eq = P / (1 + T1 I) at rate 1/T1 + I.
+ * Model 2: class A: the inversion follows the pump adiabatically; the state
+ *          holds the pump level and saturation acts through gain_amp. */
+static double inversion_next(const orc_params* p, double Nn, double P, double I)
+{
+    if (p->model == 1) {
+        double rate = 1.0 / p->T1 + I;
+        double neq = P / (1.0 + p->T1 * I);
+        return neq + (Nn - neq) * exp(-rate);
+    }
+    if (p->model == 2) return P;
+    return Nn + (P - Nn) / p->T1 - Nn * I;
 }
 
 int orc_run(const orc_params* p, double* E, double* Ninv, int n_trips,
@@ -322,17 +354,17 @@ int orc_run(const orc_params* p, double* E, double* Ninv, int n_trips,
             double I = er * er + ei * ei;            /* |E_n|^2 at the sheet */
             double Nn = Ninv[i];
             double a2 = A[2 * i] * A[2 * i] + A[2 * i + 1] * A[2 * i + 1];
-            double g = exp(0.5 * Nn);                /* frozen-inversion gain */
+            double g = gain_amp(p, Nn, I);           /* gain sheet, amplitude */
             s1 += I;
             s2 += a2 * I;
             s3 += a2 * g * g * I;
             s4 += Nn;
-            /* local step f: G = sqrt(R) A exp(N_n/2) E_n */
+            /* local step f: G = sqrt(R) A g E_n (g = exp(N_n/2) for B class) */
             double fr = sqR * g * er, fi = sqR * g * ei;
             G[2 * i] = A[2 * i] * fr - A[2 * i + 1] * fi;
             G[2 * i + 1] = A[2 * i] * fi + A[2 * i + 1] * fr;
             /* inversion: relaxation toward the pump, depletion by |E_n|^2 */
-            Ninv[i] = Nn + (P0[i] - Nn) / p->T1 - Nn * I;
+            Ninv[i] = inversion_next(p, Nn, P0[i], I);
         }
         if (trace) {
             trace[4 * (size_t)t + 0] = s1;
@@ -378,7 +410,8 @@ int orc_spectrum(const orc_params* p, const double* E, const double* Ninv,
             size_t i = (size_t)y * N + x;
             double ar, ai;
             aperture(p, y, x, &ar, &ai);
-            double g = sqR * exp(0.5 * Ninv[i]);
+            double I = E[2 * i] * E[2 * i] + E[2 * i + 1] * E[2 * i + 1];
+            double g = sqR * gain_amp(p, Ninv[i], I);
             double fr = g * E[2 * i], fi = g * E[2 * i + 1];
             G[2 * i] = ar * fr - ai * fi;
             G[2 * i + 1] = ar * fi + ai * fr;

@@ -37,6 +37,12 @@ typedef struct {
                            exp[(Delta^2/2) Laplacian] (Sec. 2.3, Eq. (18)) of
                            deviation Delta (m) replaces the Fresnel step;
                            0 = Fresnel propagation over L                       */
+    int    model;       /* local step and inversion update, sigma = 1:
+                           0 B-class laser, Eq. (1) (forward Euler, one trip)
+                           1 B-class laser, Eq. (6) integrated exactly over one
+                             trip with |E|^2 frozen
+                           2 class-A laser, Eq. (8): saturable gain
+                             N/(1 + T1|E|^2), inversion held at the pump     */
 } orc_params;
 
 /* One-dimensional DFT of length n = 2^a 3^b, in place, unnormalized.

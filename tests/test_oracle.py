@@ -407,3 +407,56 @@ def test_rg_filter_never_adds_energy_and_rejects_bad_widths():
     for bad in (-1e-6, float("nan"), float("inf")):
         with pytest.raises(ValueError):
             oracle.run(passive(n, dx, 1.064e-6, 2e-3, filter_delta=bad), e0, np.zeros((n, n)), 1)
+
+
+# --------------------------------------------- alternative local steps ----
+
+def _uniform(model, n=8, R=0.9, r=2.0, T1=50.0, **kw):
+    Nth = math.log(1 / R)
+    return CavityParams(N=n, dx=1e-5, lam=1.064e-6, L=2e-3, R=R, N0=r * Nth, T1=T1, ap_kind=0,
+                        model=model, **kw), Nth
+
+
+@pytest.mark.parametrize("I,n_start", [(0.02, 0.35), (0.4, 0.1), (2.5, 0.8)])
+def test_exact_inversion_update_solves_the_rate_equation(I, n_start):
+    """Model 1: over one round trip with |E|^2 = I frozen, the inversion of
+    Eq. (6) (sigma = 1, time in trips) obeys dN/dt = (N0 - N)/T1 - N I; the
+    oracle's update must equal an independent numerical solution of it."""
+    from scipy.integrate import solve_ivp
+
+    p, _ = _uniform(1, T1=7.0)
+    e0 = np.full((p.N, p.N), math.sqrt(I) + 0j)
+    _, ninv, _ = oracle.run(p, e0, np.full((p.N, p.N), n_start), 1)
+    sol = solve_ivp(lambda t, y: (p.N0 - y) / p.T1 - y * I, (0.0, 1.0), [n_start], rtol=1e-13, atol=1e-15)
+    assert np.max(np.abs(ninv - sol.y[0, -1])) <= 1e-11
+
+
+@pytest.mark.parametrize("model", [1, 2])
+def test_alternative_local_steps_keep_the_plane_wave_fixed_point(model):
+    """Both alternative local steps share the B-class steady state of a
+    uniform plane wave: |E*|^2 = (r - 1)/T1.  Model 1 (exact update): N* =
+    N0/(1 + T1 I*) = ln(1/R).  Model 2 (class A, Eq. (8)): the inversion stays
+    at the pump and the saturated gain N0/(1 + T1 I*) = ln(1/R) balances the
+    mirror."""
+    r, T1 = 2.0, 1000.0
+    p, Nth = _uniform(model, n=16, r=r, T1=T1)
+    I = (r - 1) / T1
+    e0 = np.full((16, 16), math.sqrt(I) * np.exp(0.7j))
+    n0 = np.full((16, 16), Nth if model == 1 else r * Nth)
+    e, ninv, _ = oracle.run(p, e0, n0, 1000)
+    assert np.max(np.abs(e - e0)) / math.sqrt(I) <= 1e-12
+    assert np.max(np.abs(ninv - n0)) <= 1e-12
+
+
+def test_class_a_small_signal_gain_is_the_b_class_gain():
+    """Far below saturation (T1 |E|^2 -> 0) the class-A gain sheet reduces to
+    the frozen-inversion gain exp(N/2) of the B-class map."""
+    p2, _ = _uniform(2, n=32, T1=10.0)
+    p0, _ = _uniform(0, n=32, T1=10.0)
+    e0 = rand_c((32, 32), 12) * 1e-7
+    n0 = np.full((32, 32), p2.N0)
+    ea, _, _ = oracle.run(p2, e0, n0, 1)
+    eb, _, _ = oracle.run(p0, e0, n0, 1)
+    assert rel(ea, eb) <= 1e-11
+    with pytest.raises(ValueError):
+        oracle.run(_uniform(3)[0], e0[:8, :8], n0[:8, :8], 1)
