@@ -119,6 +119,24 @@ typedef struct {
 int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L,
                     double F, double R, const lsr_aperture* ap, lsr_prec prec);
 
+/* Local step and inversion update (sigma = 1, time in round trips, I the
+ * intensity incident on the gain sheet, P the local pump level):
+ * LSR_MODEL_B_EULER  (default) B-class laser, Eq. (1): amplitude gain
+ *                    exp(N/2) with the inversion frozen during the pass, then
+ *                    N' = N + (P - N)/T1 - N I (forward Euler over one trip).
+ * LSR_MODEL_B_EXACT  the same gain; the rate equation of Eq. (6) integrated
+ *                    exactly over one trip with I frozen:
+ *                    N' = N_eq + (N - N_eq) exp(-(1/T1 + I)), N_eq = P/(1 + T1 I).
+ * LSR_MODEL_CLASS_A  class-A laser, Eq. (8): saturable amplitude gain
+ *                    exp(N / (2 (1 + T1 I))); the inversion state follows the
+ *                    pump, N' = P.
+ * The trace and diagnostics sums use the model's gain factor in place of
+ * exp(N).  Takes effect on the next call.  Batches run the default model
+ * only: lsr_batch_create and lsr_batch_roundtrips return LSR_EUNSUPPORTED for
+ * a plan with another model.  LSR_EINVAL for an unknown model. */
+typedef enum { LSR_MODEL_B_EULER = 0, LSR_MODEL_B_EXACT = 1, LSR_MODEL_CLASS_A = 2 } lsr_model;
+int lsr_plan_set_model(lsr_plan p, int model);
+
 /* Nonlocal step of the map: delta > 0 replaces the Fresnel propagation by
  * the real renormalization-group filter of Sec. 2.3, Eq. (18),
  * exp[(delta^2/2) d^2/dx^2] applied along both transverse axes, i.e. the

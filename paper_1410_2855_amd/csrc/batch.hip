@@ -457,6 +457,8 @@ int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count) {
         if (plans[i]->prec != PREC_FP64TAB)
             return set_err(LSR_EUNSUPPORTED, "only FP64TAB plans (FP32 field, FP64-built tables) can be batched");
         if (plans[i]->device != plans[0]->device) return set_err(LSR_EINVAL, "plans on different devices");
+        if (plans[i]->model != 0)
+            return set_err(LSR_EUNSUPPORTED, "plan %d: batches run the default local step only", i);
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return set_err(LSR_EINVAL, "plan %d appears twice", i);
     }
@@ -536,9 +538,12 @@ int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* N, int n_trip
     if (!b) return set_err(LSR_EINVAL, "batch is NULL");
     if (n_trips < 0) return set_err(LSR_EINVAL, "n_trips < 0");
     if (!E || !N) return set_err(LSR_EINVAL, "E or Ninv array is NULL");
-    for (size_t i = 0; i < b->plans.size(); ++i)
+    for (size_t i = 0; i < b->plans.size(); ++i) {
         if (!E[i] || !N[i] || ((uintptr_t)E[i] & 15u) || ((uintptr_t)N[i] & 15u))
             return set_err(LSR_EINVAL, "state %zu: NULL or not 16-byte aligned", i);
+        if (b->plans[i]->model != 0)
+            return set_err(LSR_EUNSUPPORTED, "plan %zu: batches run the default local step only", i);
+    }
     if (n_trips == 0) return LSR_OK;
     DeviceGuard dg(b->device);
     // order after the caller's work on the plans' stream, and back

@@ -43,6 +43,8 @@ struct CavDesc {
     int nrb;                // row blocks = column blocks = N / LPW
     int nbins;
     int prop_kind;          // 0 Fresnel propagator (hx), 1 real filter table (hx holds it)
+    int model;              // local step: 0 B class (Euler update), 1 B class (exact
+                            // update over a trip), 2 class A (saturable gain)
     double sqrtR;
     double N0, inv_T1, mod_amp;
     double dx;

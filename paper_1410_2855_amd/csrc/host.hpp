@@ -54,6 +54,7 @@ struct lsr_plan_s {
     lsr_aperture ap{};
     double N0 = 0, T1 = 1, mod_amp = 0, mod_period = 0;
     double filter = 0;                 // > 0: width of the real filter replacing the propagator
+    int model = 0;                     // lsr_model
     unsigned version = 0;              // bumped whenever the descriptor d changes
     hipStream_t stream = nullptr;
     const lsr::Launchers* kern = nullptr;

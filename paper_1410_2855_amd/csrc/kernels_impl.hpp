@@ -7,11 +7,11 @@
 
 namespace lsr {
 
-template <class S, typename T, int MODE>
+template <class S, typename T, int MODE, int MODEL = 0>
 __global__ __launch_bounds__(S::THREADS) void k_row(CavDesc d) {
     __shared__ cx<T> lds[S::LDS_ELEMS];
     __shared__ double red[4 * 16];
-    row_task<S, T, MODE>(d, blockIdx.x, lds, red);
+    row_task<S, T, MODE, MODEL>(d, blockIdx.x, lds, red);
 }
 
 template <class S, typename T, int MODE, int PROP>
@@ -25,17 +25,27 @@ __global__ __launch_bounds__(S::THREADS) void k_col(CavDesc d) {
     col_task<S, T, MODE, PROP>(d, blockIdx.x, lds);
 }
 
-template <class S, typename T>
-int launch_row_t(const CavDesc& d, int mode, hipStream_t st) {
+template <class S, typename T, int MODEL>
+int launch_row_m(const CavDesc& d, int mode, hipStream_t st) {
     const dim3 g(S::N / S::LPW), b(S::THREADS);
     switch (mode) {
-    case ROW_FIRST: hipLaunchKernelGGL((k_row<S, T, ROW_FIRST>), g, b, 0, st, d); break;
-    case ROW_MID:   hipLaunchKernelGGL((k_row<S, T, ROW_MID>), g, b, 0, st, d); break;
-    case ROW_LAST:  hipLaunchKernelGGL((k_row<S, T, ROW_LAST>), g, b, 0, st, d); break;
-    case ROW_DIAG:  hipLaunchKernelGGL((k_row<S, T, ROW_DIAG>), g, b, 0, st, d); break;
+    case ROW_FIRST: hipLaunchKernelGGL((k_row<S, T, ROW_FIRST, MODEL>), g, b, 0, st, d); break;
+    case ROW_MID:   hipLaunchKernelGGL((k_row<S, T, ROW_MID, MODEL>), g, b, 0, st, d); break;
+    case ROW_LAST:  hipLaunchKernelGGL((k_row<S, T, ROW_LAST>), g, b, 0, st, d); break;   // no local step
+    case ROW_DIAG:  hipLaunchKernelGGL((k_row<S, T, ROW_DIAG, MODEL>), g, b, 0, st, d); break;
     default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+template <class S, typename T>
+int launch_row_t(const CavDesc& d, int mode, hipStream_t st) {
+    switch (d.model) {
+    case 0: return launch_row_m<S, T, 0>(d, mode, st);
+    case 1: return launch_row_m<S, T, 1>(d, mode, st);
+    case 2: return launch_row_m<S, T, 2>(d, mode, st);
+    default: return -1;
+    }
 }
 
 template <class S, typename T>

@@ -248,7 +248,10 @@ __device__ __forceinline__ void finalize_sums(const CavDesc& d) {
 // Local step, inversion update and diagnostics sums on the lane's points of
 // row y (register order of the first forward radix = natural x order).  Done
 // in phases over all P points so the aperture power runs as one uniform loop.
-template <class S, typename T, int MODE>
+// MODEL selects the local step (0 B class with the Euler update, 1 B class
+// with the update exact over a trip, 2 class A); a compile-time choice, so the
+// default kernels carry no code or registers of the others.
+template <class S, typename T, int MODE, int MODEL = 0>
 __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc& d, int y, int lane,
                                            T* acc) {
     constexpr int R = R_FIRST<S>;
@@ -302,7 +305,11 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
             const cx<T> e = v[i];
             const T n = nv[i];
             const T I = fma_(e.re, e.re, e.im * e.im);
-            const T eh = ex((T)0.5 * n);          // frozen-inversion amplitude gain
+            // amplitude gain of the sheet: frozen inversion exp(N/2) (B class),
+            // or the class-A saturable gain exp(N / (2 (1 + T1 I)))
+            T eh;
+            if constexpr (MODEL == 2) eh = ex((T)0.5 * n * iT1 / (iT1 + I));
+            else eh = ex((T)0.5 * n);
             const T A2 = A[i] * A[i];
             const T aeh = A[i] * eh;
             acc[0] += I;
@@ -314,8 +321,19 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
             v[i] = g;
             if constexpr (MODE != ROW_DIAG) {
                 const T pump = pc ? N0 * fma_(mamp * gld<T>(pc, (unsigned)sizeof(T) * x), pcy, (T)1) : N0;
+                T nn;
+                if constexpr (MODEL == 0) {
+                    // forward Euler over one trip
+                    nn = fma_(-n, I, fma_(pump - n, iT1, n));
+                } else if constexpr (MODEL == 1) {
+                    // exact over one trip with I frozen: relax to N_eq at rate 1/T1 + I
+                    const T neq = pump * iT1 / (iT1 + I);
+                    nn = fma_(n - neq, ex(-(iT1 + I)), neq);
+                } else {
+                    nn = pump;   // class A: the inversion follows the pump
+                }
                 gst_nt<T, (int)sizeof(T) * (b * S::L + r * (S::N / R))>(
-                    d.Ninv, row + (unsigned)sizeof(T) * (unsigned)lane, fma_(-n, I, fma_(pump - n, iT1, n)));
+                    d.Ninv, row + (unsigned)sizeof(T) * (unsigned)lane, nn);
             }
         });
     });
@@ -352,7 +370,7 @@ __device__ __forceinline__ void row_load(const CavDesc& d, int rb, RowRegs<S, T>
 }
 
 // TWS / ltw: twiddle source (TW_LDS: ltw is the workgroup's LDS copy).
-template <class S, typename T, int MODE, int TWS = TW_GLOBAL, class Prefetch>
+template <class S, typename T, int MODE, int TWS = TW_GLOBAL, int MODEL = 0, class Prefetch>
 __device__ __forceinline__ void row_body(const CavDesc& d, int rb, cx<T>* lds, double* red, RowRegs<S, T>& in,
                                          Prefetch&& prefetch, const cx<T>* ltw = nullptr) {
     const int tid = opaque_tid();
@@ -389,7 +407,7 @@ __device__ __forceinline__ void row_body(const CavDesc& d, int rb, cx<T>* lds, d
         // per-lane sums in the field's precision (P terms), FP64 from the
         // wave reduction on
         T acc[4] = {(T)0, (T)0, (T)0, (T)0};
-        local_step<S, T, MODE>(v, nv, d, y, lane, acc);
+        local_step<S, T, MODE, MODEL>(v, nv, d, y, lane, acc);
         double accd[4] = {(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
         block_sums_store<S>(accd, red, d.partials + 4 * rb, tid);
         fft_line<S, FWD, TWS>(v, myl, lane, tw);
@@ -401,11 +419,11 @@ __device__ __forceinline__ void row_body(const CavDesc& d, int rb, cx<T>* lds, d
     }
 }
 
-template <class S, typename T, int MODE>
+template <class S, typename T, int MODE, int MODEL = 0>
 __device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, double* red) {
     RowRegs<S, T> in;
     row_load<S, T, MODE>(d, rb, in);
-    row_body<S, T, MODE>(d, rb, lds, red, in, [] {});
+    row_body<S, T, MODE, TW_GLOBAL, MODEL>(d, rb, lds, red, in, [] {});
 }
 
 // PROP: propagator form of the column pass -- PROP_TABLE multiplies by the

@@ -322,6 +322,7 @@ int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L, do
     d.phase_c = kTwoPi * 0.5 * lambda * L / ((N * dx) * (N * dx));
     d.inv_nn = 1.0 / ((double)N * (double)N);
     d.prop_kind = 0;
+    d.model = 0;
     *out = p;
     return LSR_OK;
 }
@@ -353,6 +354,15 @@ int lsr_plan_set_gain(lsr_plan p, double N0, double T1, double mod_amp, double m
     p->d.inv_T1 = 1.0 / T1;
     p->d.mod_amp = modulated ? mod_amp : 0.0;
     p->d.pump_c = modulated ? p->d_pump : nullptr;
+    ++p->version;
+    return LSR_OK;
+}
+
+int lsr_plan_set_model(lsr_plan p, int model) {
+    if (!p) return set_err(LSR_EINVAL, "plan is NULL");
+    if (model < LSR_MODEL_B_EULER || model > LSR_MODEL_CLASS_A) return set_err(LSR_EINVAL, "model %d out of range", model);
+    p->model = model;
+    p->d.model = model;
     ++p->version;
     return LSR_OK;
 }

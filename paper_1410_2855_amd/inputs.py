@@ -52,6 +52,7 @@ class Cavity:
     mod_periods: int = 0     # integer number of pump periods across the window
     n0_override: float | None = None
     filter_delta: float = 0.0  # > 0: real renormalization-group filter (m) instead of Fresnel
+    model: int = 0             # 0 B class (Euler update), 1 B class (exact update), 2 class A
 
     @property
     def a(self) -> float:
@@ -103,7 +104,7 @@ def oracle_params(cav: Cavity):
                         N0=cav.N0, T1=cav.T1, focal=cav.focal, ap_kind=cav.ap_kind,
                         ap_radius=cav.ap_radius, ap_order=cav.ap_order,
                         mod_amp=cav.mod_amp, mod_period=cav.mod_period,
-                        filter_delta=cav.filter_delta)
+                        filter_delta=cav.filter_delta, model=cav.model)
 
 
 # --------------------------------------------------------------------------

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liblsr.so")
 LSR_OK, LSR_EINVAL, LSR_ENOMEM, LSR_EDEVICE, LSR_EUNSUPPORTED, LSR_ENONFINITE = 0, -1, -2, -3, -4, -5
 LSR_PREC_PLAIN, LSR_PREC_FP64TAB, LSR_PREC_FP64 = 0, 1, 2
 LSR_AP_NONE, LSR_AP_SUPERGAUSS, LSR_AP_GAUSS, LSR_AP_MASK = 0, 1, 2, 3
+LSR_MODEL_B_EULER, LSR_MODEL_B_EXACT, LSR_MODEL_CLASS_A = 0, 1, 2
 
 _STATUS = {0: "LSR_OK", -1: "LSR_EINVAL", -2: "LSR_ENOMEM", -3: "LSR_EDEVICE",
            -4: "LSR_EUNSUPPORTED", -5: "LSR_ENONFINITE"}
@@ -51,6 +52,7 @@ _SIGS = {
     "lsr_plan_create": (_i, [ctypes.POINTER(_vp), _i, _d, _d, _d, _d, _d, ctypes.POINTER(lsr_aperture), _i]),
     "lsr_plan_set_gain": (_i, [_vp, _d, _d, _d, _d]),
     "lsr_plan_set_filter": (_i, [_vp, _d]),
+    "lsr_plan_set_model": (_i, [_vp, _i]),
     "lsr_plan_set_stream": (_i, [_vp, _vp]),
     "lsr_roundtrips": (_i, [_vp, _vp, _vp, _i]),
     "lsr_sync": (_i, [_vp]),
@@ -176,6 +178,10 @@ def lsr_plan_set_filter(plan, delta: float):
     _check(load().lsr_plan_set_filter(plan, float(delta)))
 
 
+def lsr_plan_set_model(plan, model: int):
+    _check(load().lsr_plan_set_model(plan, int(model)))
+
+
 def lsr_plan_set_stream(plan, stream):
     _check(load().lsr_plan_set_stream(plan, _stream_handle(stream)))
 
@@ -292,6 +298,8 @@ class Plan:
         lsr_plan_set_gain(self.handle, cav.N0, cav.T1, cav.mod_amp, cav.mod_period)
         if getattr(cav, "filter_delta", 0.0):
             lsr_plan_set_filter(self.handle, cav.filter_delta)
+        if getattr(cav, "model", 0):
+            lsr_plan_set_model(self.handle, cav.model)
         lsr_plan_set_stream(self.handle, stream if stream is not None else torch.cuda.current_stream())
 
     @property
