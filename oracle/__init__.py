@@ -73,8 +73,9 @@ def _load():
         lib.orc_run.argtypes = [ctypes.POINTER(_Params), dp, dp, ctypes.c_int, dp]
         lib.orc_nbins.argtypes = [ctypes.c_int]
         lib.orc_spectrum.argtypes = [ctypes.POINTER(_Params), dp, dp, dp, ctypes.c_int]
+        lib.orc_propagate.argtypes = [ctypes.POINTER(_Params), dp, ctypes.c_double]
         for f in ("orc_fft1d", "orc_dft_brute1d", "orc_fft2", "orc_dft_brute2d",
-                  "orc_run", "orc_nbins", "orc_spectrum"):
+                  "orc_run", "orc_nbins", "orc_spectrum", "orc_propagate"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -177,6 +178,18 @@ def run(params: CavityParams, E, Ninv, n_trips: int):
     if rc != 0:
         raise ValueError("orc_run: invalid parameters")
     return e, ninv, trace
+
+
+def propagate(params: CavityParams, E, z: float) -> np.ndarray:
+    """E propagated freely over z metres (no local step)."""
+    n = params.N
+    e = _c128(E).reshape(n, n).copy()
+    p, keep = params._c()
+    rc = _load().orc_propagate(ctypes.byref(p), _dp(e.view(np.float64)), float(z))
+    del keep
+    if rc != 0:
+        raise ValueError("orc_propagate: invalid arguments")
+    return e
 
 
 def nbins(N: int) -> int:

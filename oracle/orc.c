@@ -389,6 +389,29 @@ fail:
     return -1;
 }
 
+int orc_propagate(const orc_params* p, double* E, double z)
+{
+    if (!params_ok(p) || !E || !(z >= 0.0) || !isfinite(z)) return -1;
+    const int N = p->N;
+    const size_t NN = (size_t)N * N;
+    if (orc_fft2(E, N, 0)) return -1;
+    for (int q = 0; q < N; q++)
+        for (int pp = 0; pp < N; pp++) {
+            double fx = signed_index(pp, N) / (N * p->dx);
+            double fy = signed_index(q, N) / (N * p->dx);
+            double ph = M_PI * p->lambda * z * (fx * fx + fy * fy);
+            size_t i = (size_t)q * N + pp;
+            double hr = cos(ph), hi = -sin(ph);
+            double er = E[2 * i], ei = E[2 * i + 1];
+            E[2 * i] = er * hr - ei * hi;
+            E[2 * i + 1] = er * hi + ei * hr;
+        }
+    if (orc_fft2(E, N, 1)) return -1;
+    const double inv_nn = 1.0 / ((double)N * (double)N);
+    for (size_t i = 0; i < 2 * NN; i++) E[i] *= inv_nn;
+    return 0;
+}
+
 int orc_nbins(int N)
 {
     /* largest radius is |(N/2, N/2)| = N / sqrt(2) */

@@ -72,6 +72,12 @@ int  orc_dft_brute2d(const double* in, double* out, int n, int inverse);
 int  orc_run(const orc_params* p, double* E, double* Ninv, int n_trips,
              double* trace);
 
+/* Free propagation over a distance z >= 0 (m), no local step: E is replaced
+ * by IFFT2( exp(-i pi lambda z (fx^2 + fy^2)) FFT2(E) ) (the operator
+ * exponent of Sec. 2.3, Eq. (25), for length z).  Uses N, dx and lambda of p.
+ * Returns 0, or -1 for invalid arguments. */
+int  orc_propagate(const orc_params* p, double* E, double z);
+
 /* Number of radial bins of the far-field spectrum for an N-point grid. */
 int  orc_nbins(int N);
 

@@ -460,3 +460,55 @@ def test_class_a_small_signal_gain_is_the_b_class_gain():
     assert rel(ea, eb) <= 1e-11
     with pytest.raises(ValueError):
         oracle.run(_uniform(3)[0], e0[:8, :8], n0[:8, :8], 1)
+
+
+# ------------------------------------------- free propagation to a plane ----
+
+def test_propagate_gaussian_beam_closed_form():
+    """Free propagation over z of exp(-r^2/w0^2) gives the textbook spreading
+    exp(-r^2 / (w0^2 (1 + i s))) / (1 + i s), s = lambda z / (pi w0^2)."""
+    n, lam = 256, 1.064e-6
+    dx = 4e-6
+    w0 = 20 * dx
+    p = passive(n, dx, lam, 2e-3)
+    X, Y = grid(n, dx)
+    r2 = X ** 2 + Y ** 2
+    for z in (0.0, 1e-4, 7e-4):
+        e = oracle.propagate(p, np.exp(-r2 / w0 ** 2), z)
+        s = lam * z / (math.pi * w0 ** 2)
+        assert rel(e, np.exp(-r2 / (w0 ** 2 * (1 + 1j * s))) / (1 + 1j * s)) <= 1e-12
+
+
+def test_propagate_fractional_talbot_planes():
+    """Sec. 5 (fractional Talbot planes): a field of period d whose spectrum
+    sits on harmonics k/d returns at z_T = 2 d^2/lambda; at z_T/2 it is shifted
+    by half a period; at z_T/4 the factor exp(-i pi lambda z k^2/d^2) per axis
+    is 1 for even harmonics k and -i for odd ones (k^2 = 1 mod 8)."""
+    n, M = 256, 16                       # period d = n/M samples
+    lam, dx = 1.064e-6, 5e-6
+    d = n // M * dx
+    zT = 2 * d ** 2 / lam
+    p = passive(n, dx, lam, 2e-3)
+    e0 = _talbot_field(n, M, 5)
+    assert rel(oracle.propagate(p, e0, zT), e0) <= 1e-12
+    half = oracle.propagate(p, e0, zT / 2)
+    s = n // M // 2
+    assert rel(half, np.roll(np.roll(e0, s, 0), s, 1)) <= 1e-12
+    spec = np.fft.fft2(e0)
+    k = np.fft.fftfreq(n, 1.0 / n)
+    kx = np.rint(k / M).astype(int)
+    KX, KY = np.meshgrid(kx, kx, indexing="xy")
+    factor = np.where(KX % 2 == 1, -1j, 1.0) * np.where(KY % 2 == 1, -1j, 1.0)
+    want = np.fft.ifft2(spec * factor)
+    assert rel(oracle.propagate(p, e0, zT / 4), want) <= 1e-12
+
+
+def test_propagate_composes_and_rejects_bad_distances():
+    n, dx = 64, 1e-5
+    p = passive(n, dx, 1.064e-6, 2e-3)
+    e0 = rand_c((n, n), 9)
+    a = oracle.propagate(p, oracle.propagate(p, e0, 3e-4), 5e-4)
+    assert rel(a, oracle.propagate(p, e0, 8e-4)) <= 1e-13
+    for bad in (-1e-3, float("nan"), float("inf")):
+        with pytest.raises(ValueError):
+            oracle.propagate(p, e0, bad)
