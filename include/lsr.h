@@ -115,7 +115,7 @@ typedef struct {
  * stream to the null stream.  Tables are built in FP64 on the host and
  * uploaded once; no allocation happens in later calls except lsr_diag's
  * first use of its spectrum scratch and table replacement by
- * lsr_plan_set_gain / lsr_plan_set_filter. */
+ * lsr_plan_set_gain / lsr_plan_set_filter / lsr_propagate. */
 int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L,
                     double F, double R, const lsr_aperture* ap, lsr_prec prec);
 
@@ -136,6 +136,18 @@ int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L,
  * a plan with another model.  LSR_EINVAL for an unknown model. */
 typedef enum { LSR_MODEL_B_EULER = 0, LSR_MODEL_B_EXACT = 1, LSR_MODEL_CLASS_A = 2 } lsr_model;
 int lsr_plan_set_model(lsr_plan p, int model);
+
+/* Free propagation of a field over a distance z (m), without the local step:
+ * E_out = IFFT2( exp(-i pi lambda z (fx^2 + fy^2)) FFT2(E_in) ), the operator
+ * exponent of Sec. 2.3, Eq. (25) for length z.  Used to record the field or
+ * intensity at intermediate planes, e.g. the fractional Talbot planes of Sec. 5
+ * (z = p^2 / (2 lambda m) for a pattern of period p).  E_in and E_out: device
+ * N*N row-major complex fields of the plan's precision; they may be the same
+ * buffer.  The phase table for z is built in FP64 and reduced mod one turn.
+ * Asynchronous on the plan's stream; waits for that stream first and
+ * allocates the table (the previous one is freed).  The plan's trace and
+ * inversion are untouched.  LSR_EINVAL for z < 0 or non-finite. */
+int lsr_propagate(lsr_plan p, const void* E_in, double z, void* E_out);
 
 /* Nonlocal step of the map: delta > 0 replaces the Fresnel propagation by
  * the real renormalization-group filter of Sec. 2.3, Eq. (18),

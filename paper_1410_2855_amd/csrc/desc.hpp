@@ -12,8 +12,11 @@ enum ApKind : int { AP_NONE = 0, AP_SUPERGAUSS = 1, AP_GAUSS = 2, AP_MASK = 3 };
 // of the previous trip, LAST finishes the inverse transform and writes the
 // row-major state, DIAG evaluates the local step and forward row transform
 // of a state into scratch without touching the state.
-enum RowMode : int { ROW_FIRST = 0, ROW_MID = 1, ROW_LAST = 2, ROW_DIAG = 3 };
-enum ColMode : int { COL_PROP = 0, COL_DIAG = 1 };
+// ROW_FWD: forward row transform of a row-major field (E) into the tiled
+// scratch, no local step (free propagation of a field copy).
+enum RowMode : int { ROW_FIRST = 0, ROW_MID = 1, ROW_LAST = 2, ROW_DIAG = 3, ROW_FWD = 4 };
+// COL_FREE: the propagator multiply without folding the trip's sums.
+enum ColMode : int { COL_PROP = 0, COL_DIAG = 1, COL_FREE = 2 };
 
 // Counters of a cavity (device, 16 words):
 //  [0] trips completed (trace ring slot of the next trip)

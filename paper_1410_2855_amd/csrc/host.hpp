@@ -65,6 +65,7 @@ struct lsr_plan_s {
     void* d_hx = nullptr;
     void* d_pump = nullptr;
     void* d_foc = nullptr;
+    void* d_hz = nullptr;            // propagator table of the last lsr_propagate distance
     double* d_partials = nullptr;
     double* d_trace = nullptr;
     unsigned* d_counters = nullptr;

@@ -33,6 +33,7 @@ int launch_row_m(const CavDesc& d, int mode, hipStream_t st) {
     case ROW_MID:   hipLaunchKernelGGL((k_row<S, T, ROW_MID, MODEL>), g, b, 0, st, d); break;
     case ROW_LAST:  hipLaunchKernelGGL((k_row<S, T, ROW_LAST>), g, b, 0, st, d); break;   // no local step
     case ROW_DIAG:  hipLaunchKernelGGL((k_row<S, T, ROW_DIAG, MODEL>), g, b, 0, st, d); break;
+    case ROW_FWD:   hipLaunchKernelGGL((k_row<S, T, ROW_FWD>), g, b, 0, st, d); break;     // no local step
     default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -3;
@@ -59,6 +60,7 @@ int launch_col_t(const CavDesc& d, int mode, hipStream_t st) {
         else hipLaunchKernelGGL((k_col<S, T, COL_PROP, PROP_TABLE>), g, b, 0, st, d);
         break;
     case COL_DIAG: hipLaunchKernelGGL((k_col<S, T, COL_DIAG, PROP_TABLE>), g, b, 0, st, d); break;
+    case COL_FREE: hipLaunchKernelGGL((k_col<S, T, COL_FREE, PROP_TABLE>), g, b, 0, st, d); break;
     default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -3;

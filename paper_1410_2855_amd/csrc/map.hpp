@@ -356,7 +356,7 @@ __device__ __forceinline__ void row_load(const CavDesc& d, int rb, RowRegs<S, T>
     const int line = tid / S::L, lane = tid % S::L;
     const int y = rb * S::LPW + line;
     constexpr int RF = R_FIRST<S>;
-    if constexpr (MODE != ROW_LAST) {
+    if constexpr (MODE != ROW_LAST && MODE != ROW_FWD) {
         const unsigned row = (unsigned)y * (unsigned)S::N * (unsigned)sizeof(T);
         sfor<0, S::P / RF>([&](auto bc) {
             sfor<0, RF>([&](auto rc) {
@@ -383,8 +383,9 @@ __device__ __forceinline__ void row_body(const CavDesc& d, int rb, cx<T>* lds, d
     constexpr int RL = R_LAST<S>;
 
     T nv[S::P];
-    if constexpr (MODE != ROW_LAST) sfor<0, S::P>([&](auto ic) { nv[decltype(ic)::value] = in.nv[decltype(ic)::value]; });
-    if constexpr (MODE == ROW_FIRST || MODE == ROW_DIAG) commit_rows<S, T, 0>(in.q, lds, tid);
+    if constexpr (MODE != ROW_LAST && MODE != ROW_FWD)
+        sfor<0, S::P>([&](auto ic) { nv[decltype(ic)::value] = in.nv[decltype(ic)::value]; });
+    if constexpr (MODE == ROW_FIRST || MODE == ROW_DIAG || MODE == ROW_FWD) commit_rows<S, T, 0>(in.q, lds, tid);
     else commit_rows<S, T, 1>(in.q, lds, tid);
     __syncthreads();
     prefetch();
@@ -406,15 +407,18 @@ __device__ __forceinline__ void row_body(const CavDesc& d, int rb, cx<T>* lds, d
     } else {
         // per-lane sums in the field's precision (P terms), FP64 from the
         // wave reduction on
-        T acc[4] = {(T)0, (T)0, (T)0, (T)0};
-        local_step<S, T, MODE, MODEL>(v, nv, d, y, lane, acc);
-        double accd[4] = {(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
-        block_sums_store<S>(accd, red, d.partials + 4 * rb, tid);
+        if constexpr (MODE != ROW_FWD) {
+            T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+            local_step<S, T, MODE, MODEL>(v, nv, d, y, lane, acc);
+            double accd[4] = {(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
+            block_sums_store<S>(accd, red, d.partials + 4 * rb, tid);
+        }
         fft_line<S, FWD, TWS>(v, myl, lane, tw);
         scatter_out<S, RL>(v, myl, lane);
         __syncthreads();
         cx<T>* dst = blk;
-        if constexpr (MODE == ROW_DIAG) dst = static_cast<cx<T>*>(d.scratch) + (size_t)rb * S::LPW * S::N;
+        if constexpr (MODE == ROW_DIAG || MODE == ROW_FWD)
+            dst = static_cast<cx<T>*>(d.scratch) + (size_t)rb * S::LPW * S::N;
         stage_out_rows<S, T, 1>(dst, lds, tid);
     }
 }

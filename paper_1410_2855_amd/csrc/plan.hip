@@ -151,7 +151,7 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 static void free_plan_memory(lsr_plan_s* p) {
     void* bufs[] = {p->d_tw, p->d_hx, p->d_pump, p->d_foc, p->d_partials, p->d_trace,
-                    p->d_counters, p->d_scratch, p->d_radial_part, p->d_diag_out};
+                    p->d_counters, p->d_scratch, p->d_radial_part, p->d_diag_out, p->d_hz};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -561,6 +561,30 @@ int lsr_diag(lsr_plan p, const void* E, const void* Ninv, lsr_diag_out* out) {
     if (out->radial) memcpy(out->radial, h.data() + 4, sizeof(double) * (size_t)nb);
     if (!std::isfinite(h[0]) || !std::isfinite(h[3]))
         return set_err(LSR_ENONFINITE, "non-finite state passed to lsr_diag");
+    return LSR_OK;
+}
+
+int lsr_propagate(lsr_plan p, const void* E_in, double z, void* E_out) {
+    if (!p) return set_err(LSR_EINVAL, "plan is NULL");
+    if (!(z >= 0) || !std::isfinite(z)) return set_err(LSR_EINVAL, "z must be >= 0 and finite");
+    if (!E_in || !E_out || !aligned16(E_in) || !aligned16(E_out)) return set_err(LSR_EINVAL, "bad E_in/E_out pointer");
+    DeviceGuard g(p->device);
+    // the previous call's table may still be in use
+    LSR_HIP(hipStreamSynchronize(p->stream));
+    if (p->d_hz) (void)hipFree(p->d_hz);
+    p->d_hz = nullptr;
+    int rc = upload(&p->d_hz, build_hx(p->N, p->dx, p->lambda, z), p->prec != PREC_FP64);
+    if (rc) return rc;
+    CavDesc d = p->d;
+    d.E = const_cast<void*>(E_in);
+    d.scratch = E_out;
+    rc = p->kern->row(d, ROW_FWD, p->stream);
+    d.E = E_out;
+    d.hx = p->d_hz;
+    d.prop_kind = 1;   // table form in every precision
+    if (rc == 0) rc = p->kern->col(d, COL_FREE, p->stream);
+    if (rc == 0) rc = p->kern->row(d, ROW_LAST, p->stream);
+    if (rc != 0) return set_err(LSR_EDEVICE, "propagate launch failed: %s", hipGetErrorString(hipGetLastError()));
     return LSR_OK;
 }
 

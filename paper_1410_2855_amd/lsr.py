@@ -53,6 +53,7 @@ _SIGS = {
     "lsr_plan_set_gain": (_i, [_vp, _d, _d, _d, _d]),
     "lsr_plan_set_filter": (_i, [_vp, _d]),
     "lsr_plan_set_model": (_i, [_vp, _i]),
+    "lsr_propagate": (_i, [_vp, _vp, _d, _vp]),
     "lsr_plan_set_stream": (_i, [_vp, _vp]),
     "lsr_roundtrips": (_i, [_vp, _vp, _vp, _i]),
     "lsr_sync": (_i, [_vp]),
@@ -180,6 +181,10 @@ def lsr_plan_set_filter(plan, delta: float):
 
 def lsr_plan_set_model(plan, model: int):
     _check(load().lsr_plan_set_model(plan, int(model)))
+
+
+def lsr_propagate(plan, E_in, z: float, E_out):
+    _check(load().lsr_propagate(plan, _ptr(E_in), float(z), _ptr(E_out)))
 
 
 def lsr_plan_set_stream(plan, stream):
@@ -327,6 +332,13 @@ class Plan:
 
     def trace(self, capacity: int) -> np.ndarray:
         return lsr_trace(self.handle, capacity)
+
+    def propagate(self, E, z: float, out=None):
+        """The field E propagated freely over z metres (new tensor unless out)."""
+        import torch
+        out = torch.empty_like(E) if out is None else out
+        lsr_propagate(self.handle, E, z, out)
+        return out
 
     def diag(self, E, Ninv) -> dict:
         return lsr_diag(self.handle, E, Ninv)

@@ -1,0 +1,86 @@
+"""Free propagation of a field to an intermediate plane (lsr_propagate) on the
+GPU against the FP64 oracle: fractional Talbot planes (Sec. 5) of the
+periodic-pump workload and of a periodic field, every precision form."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1410_2855_amd.inputs import Cavity, initial_state, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1410_2855_amd import lsr  # noqa: E402
+
+TAB, PLAIN, F64 = lsr.LSR_PREC_FP64TAB, lsr.LSR_PREC_PLAIN, lsr.LSR_PREC_FP64
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.mark.parametrize("prec,tol", [(TAB, 2e-6), (PLAIN, 1e-5), (F64, 1e-12)])
+@pytest.mark.parametrize("N", [256, 768, 2048])
+def test_propagate_matches_oracle(N, prec, tol):
+    if not lsr.lsr_supported(N, prec):
+        pytest.skip("not compiled")
+    cav = Cavity(N=N, F=300.0, R=0.9, pump_ratio=2.0, T1=1000.0, index=3, mod_amp=0.3, mod_periods=16)
+    e0, _ = initial_state(cav)
+    p = lsr.Plan(cav, prec=prec)
+    e, _ = p.state(e0, np.zeros((N, N)))
+    d = 2 * cav.a / cav.mod_periods
+    zT = 2 * d * d / cav.lam
+    for m in (1, 2, 3, 4):          # fractional Talbot planes z_T / m
+        out = p.propagate(e, zT / m)
+        torch.cuda.synchronize()
+        want = oracle.propagate(oracle_params(cav), e0, zT / m)
+        # FP64: both sides carry ~1 ulp of the phase argument, whose largest
+        # value (at the Nyquist corner) reaches ~5e4 rad at 2048^2
+        max_phase = math.pi * cav.lam * zT / m * 2 * (1 / (2 * cav.dx)) ** 2
+        assert rel(out.cpu().numpy(), want) <= tol + max_phase * 4e-16, m
+    p.close()
+
+
+def test_propagate_in_place_and_talbot_revival():
+    """In place (E_in == E_out); a field of period d comes back at z_T."""
+    N, M = 512, 16
+    cav = Cavity(N=N, F=200.0, R=0.9, pump_ratio=2.0, T1=1000.0)
+    r = np.random.default_rng(2)
+    spec = np.zeros((N, N), complex)
+    idx = np.arange(-4, 5) * M % N
+    for iy in idx:
+        for ix in idx:
+            spec[iy, ix] = r.standard_normal() + 1j * r.standard_normal()
+    e0 = np.fft.ifft2(spec) * N
+    p = lsr.Plan(cav)
+    e, _ = p.state(e0, np.zeros((N, N)))
+    d = N // M * cav.dx
+    lsr.lsr_propagate(p.handle, e, 2 * d * d / cav.lam, e)
+    p.sync()
+    assert rel(e.cpu().numpy(), e0) <= 2e-6
+    p.close()
+
+
+def test_propagate_leaves_the_cavity_state_and_trace_alone():
+    cav = Cavity(N=256, F=100.0, R=0.9, pump_ratio=2.0, T1=1000.0, index=7)
+    e0, n0 = initial_state(cav)
+    p = lsr.Plan(cav)
+    e, n = p.state(e0, n0)
+    p.roundtrips(e, n, 5)
+    tr = p.trace(5)
+    e_keep, n_keep = e.clone(), n.clone()
+    _ = p.propagate(e, 1e-3)
+    p.roundtrips(e, n, 0)
+    p.sync()
+    assert torch.equal(e, e_keep) and torch.equal(n, n_keep)
+    assert np.array_equal(p.trace(5), tr)
+    for bad in (-1.0, math.nan, math.inf):
+        with pytest.raises(lsr.LsrError) as ei:
+            lsr.lsr_propagate(p.handle, e, bad, e)
+        assert ei.value.code == lsr.LSR_EINVAL
+    p.close()
