@@ -156,6 +156,9 @@ WORKLOADS = {
 }
 
 
+LOCAL_STEPS = {"b-euler": 0, "b-exact": 1, "class-a": 2}
+
+
 def make_workload(name: str, cavities: int):
     from paper_1410_2855_amd.inputs import structured_4096, sweep, sweep_1024
 
@@ -196,6 +199,12 @@ def main():
                     help="sweep1024 (default, the metric's configuration): 1024^2 cavities with the sweep's "
                          "parameter draws; sweep512: 512 cavities of N in {256..1024}; structured4096: "
                          "16 cavities at 4096^2 with the periodic pump")
+    ap.add_argument("--local-step", choices=sorted(LOCAL_STEPS), default="b-euler",
+                    help="local step of the map; other than b-euler the cavities run one launch sequence "
+                         "each (batches run the default local step only)")
+    ap.add_argument("--filter-delta", type=float, default=0.0,
+                    help="> 0: the renormalization-group filter of this width, in grid spacings, "
+                         "replaces the Fresnel step")
     ap.add_argument("--autotune", action="store_true", help="retune the batch and update the cache")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
@@ -226,6 +235,11 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     cavs, workload = make_workload(args.workload, args.cavities)
+    model = LOCAL_STEPS[args.local_step]
+    if model or args.filter_delta > 0:
+        cavs = [c.with_(model=model, filter_delta=args.filter_delta * c.dx) for c in cavs]
+        workload += "; local step %s%s" % (args.local_step, ", filter %.3g dx" % args.filter_delta
+                                           if args.filter_delta > 0 else "")
     plans, Es, Ns = [], [], []
     for c in cavs:
         p = lsr.Plan(c, prec=lsr.LSR_PREC_FP64TAB, stream=stream)
@@ -235,6 +249,36 @@ def main():
         Ns.append(n)
     torch.cuda.synchronize()
     pts = sum(c.N * c.N for c in cavs)
+
+    def run_plain(k):
+        for p, e, n in zip(plans, Es, Ns):
+            p.roundtrips(e, n, k)
+
+    if model:
+        # one launch sequence per cavity; kernel times from the first cavity
+        run_plain(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_plain(args.steps)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        rms, cms = lsr.lsr_time_kernels(plans[0].handle, Es[0], Ns[0], 20)
+        p0 = cavs[0].N ** 2
+        for p in plans:
+            p.sync()
+        print(json.dumps({
+            "metric": "grid-pts x round-trips/s (one launch sequence per cavity)", "value": pts / t,
+            "unit": "grid-pts*round-trips/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "c64", "data": "synthetic",
+            "config": {"workload": workload, "cavities": len(cavs), "mode": "plain"},
+            "kernels_first_cavity_ms": {"row_pass": rms, "column_pass": cms,
+                                        "row_GBps": ROW_BYTES_PER_PT * p0 / (rms * 1e-3) / 1e9,
+                                        "column_GBps": COL_BYTES_PER_PT * p0 / (cms * 1e-3) / 1e9}}), flush=True)
+        for p in plans:
+            p.close()
+        return
+
     batch = lsr.lsr_batch_create([p.handle for p in plans])
     if args.autotune:
         lsr.lsr_autotune(None, batch, TUNE_CACHE)
@@ -242,10 +286,6 @@ def main():
 
     def run_batched(k):
         lsr.lsr_batch_roundtrips(batch, Es, Ns, k)
-
-    def run_plain(k):
-        for p, e, n in zip(plans, Es, Ns):
-            p.roundtrips(e, n, k)
 
     def timed(fn, steps, warmup):
         fn(warmup)
