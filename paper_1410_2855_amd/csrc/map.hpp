@@ -18,8 +18,8 @@
 // elements row-major inside a tile.  Row block rb (rows rb*LPW..) is then one
 // contiguous span, exactly the span rows rb*LPW.. occupy in row-major order,
 // so the first and last row passes convert in place; column block cb is N/LPW
-// contiguous tiles.  Every global access is a whole tile (>= 128 B for the
-// FP32 shapes), independent of N.
+// tiles, each contiguous, one row block apart.  Every global access covers
+// whole tiles (>= 128 B for the FP32 shapes), independent of N.
 #pragma once
 
 #include "desc.hpp"
