@@ -1,6 +1,8 @@
-// batch_impl.hpp -- one persistent kernel per round trip for many cavities.
+// batch_impl.hpp -- kernels that advance many cavities together: the grouped
+// passes (one launch per pass: k_pass, and its software-pipelined form
+// k_pass_pipe) and the persistent round-trip kernel k_trip described here.
 //
-// All cavities of a group advance one round trip per launch.  The work of a
+// k_trip: all cavities of a group advance one round trip per launch.  The work of a
 // trip is a list of tasks (row blocks and column blocks of every cavity),
 // ordered by the host packer so that a cavity's column tasks come after all
 // of its row tasks.  Workgroups take tickets from an atomic queue in chunks
