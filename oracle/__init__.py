@@ -57,6 +57,7 @@ class _Params(ctypes.Structure):
         ("mod_period", ctypes.c_double),
         ("filter_delta", ctypes.c_double),
         ("model", ctypes.c_int),
+        ("slices", ctypes.c_int),
     ]
 
 
@@ -109,6 +110,7 @@ class CavityParams:
     mod_period: float = 0.0
     filter_delta: float = 0.0   # > 0: Gaussian renormalization-group filter instead of Fresnel
     model: int = 0              # 0 B class (Euler), 1 B class (exact over a trip), 2 class A
+    slices: int = 1             # thin gain sheets per iterate (inversion holds one N x N map each)
 
     def _c(self):
         p = _Params()
@@ -118,6 +120,7 @@ class CavityParams:
         p.N0, p.T1, p.mod_amp, p.mod_period = self.N0, self.T1, self.mod_amp, self.mod_period
         p.filter_delta = self.filter_delta
         p.model = self.model
+        p.slices = self.slices
         keep = None
         if self.ap_kind == 3:
             keep = np.ascontiguousarray(self.ap_mask, dtype=np.float64).reshape(self.N, self.N)
@@ -165,11 +168,13 @@ def run(params: CavityParams, E, Ninv, n_trips: int):
 
     ``trace`` has shape (n_trips, 4): raw sums S1 = sum|E|^2,
     S2 = sum|A|^2|E|^2, S3 = sum|A|^2 e^N |E|^2, S4 = sum N of each trip's
-    incoming state.
+    incoming state.  With ``params.slices`` = m > 1, ``Ninv`` holds the m
+    sheets' inversions, shape (m, N, N), and the sums are those of sheet 0.
     """
     n = params.N
+    m = max(int(params.slices), 1)
     e = _c128(E).reshape(n, n).copy()
-    ninv = np.ascontiguousarray(Ninv, dtype=np.float64).reshape(n, n).copy()
+    ninv = np.ascontiguousarray(Ninv, dtype=np.float64).reshape((m, n, n) if m > 1 else (n, n)).copy()
     trace = np.zeros((max(n_trips, 0), 4), dtype=np.float64)
     p, keep = params._c()
     rc = _load().orc_run(ctypes.byref(p), _dp(e.view(np.float64)), _dp(ninv),

@@ -33,6 +33,13 @@
  *    E_n is the field at the gain sheet before the local step.
  *  - grid: x_j = (j - N/2) dx; signed frequency index p~ = p (p < N/2) else
  *    p - N; fx = p~ / (N dx).  Forward DFT unnormalized, inverse scaled 1/N^2.
+ *  - several gain sheets: the paper names, only by reference, the variant in
+ *    which the active medium is spread along the cavity as thin sheets, each
+ *    with its own inversion (Sec. 2.2, after Eq. (12)).  Read as m equally
+ *    spaced sheets per iterate, free propagation over L/m after each; the
+ *    mirror and aperture act at sheet 0, which holds the state; each sheet
+ *    has pump N0/m, the same T1 and local-step model, and is depleted by the
+ *    field incident on it.  m = 1 is Eq. (1) exactly.
  */
 #include "orc.h"
 
@@ -221,6 +228,7 @@ static int params_ok(const orc_params* p)
     if (p->ap_kind == 3 && !p->ap_mask) return 0;
     if (!(p->filter_delta >= 0.0) || !isfinite(p->filter_delta)) return 0;
     if (p->model < 0 || p->model > 2) return 0;
+    if (p->slices < 0) return 0;
     return 1;
 }
 
@@ -308,8 +316,10 @@ int orc_run(const orc_params* p, double* E, double* Ninv, int n_trips,
     if (!params_ok(p) || !E || !Ninv || n_trips < 0) return -1;
     const int N = p->N;
     const size_t NN = (size_t)N * N;
+    /* m thin sheets per iterate (Sec. 2.2, after Eq. (12)); m = 1 is Eq. (1) */
+    const int m = p->slices > 1 ? p->slices : 1;
     double* A = (double*)malloc(sizeof(double) * 2 * NN);   /* complex aperture */
-    double* P0 = (double*)malloc(sizeof(double) * NN);      /* pump map */
+    double* P0 = (double*)malloc(sizeof(double) * NN);      /* pump map of one sheet */
     double* H = (double*)malloc(sizeof(double) * 2 * NN);   /* transfer function */
     double* G = (double*)malloc(sizeof(double) * 2 * NN);
     if (!A || !P0 || !H || !G) { free(A); free(P0); free(H); free(G); return -1; }
@@ -318,28 +328,33 @@ int orc_run(const orc_params* p, double* E, double* Ninv, int n_trips,
         for (int x = 0; x < N; x++) {
             size_t i = (size_t)y * N + x;
             aperture(p, y, x, &A[2 * i], &A[2 * i + 1]);
-            P0[i] = pump(p, y, x);
+            /* each of the m sheets holds 1/m of the medium's pumped gain */
+            P0[i] = pump(p, y, x) / (double)m;
         }
     /* Free-space transfer function of the operator exponent exp[iL/(2k) Lap]
      * (Sec. 2.3, Eq. (25)): the Laplacian is -4 pi^2 (fx^2 + fy^2) in Fourier
      * space and k = 2 pi / lambda, so H = exp(-i pi lambda L (fx^2 + fy^2)).
-     * It is the Fourier transform of the Fresnel kernel of Eqs. (11), (13). */
+     * It is the Fourier transform of the Fresnel kernel of Eqs. (11), (13).
+     * With m sheets it is taken for the distance L/m between two sheets. */
     /* With filter_delta > 0 the nonlocal step is instead the real kernel of
      * the renormalization-group fixed point (Sec. 2.3, Eq. (18)), the
      * operator exp[(Delta^2/2) d^2/dx^2] applied along both transverse axes:
      * in Fourier space d^2/dx^2 -> -4 pi^2 fx^2, so
-     * H = exp(-2 pi^2 Delta^2 (fx^2 + fy^2)), real and at most 1. */
+     * H = exp(-2 pi^2 Delta^2 (fx^2 + fy^2)), real and at most 1.  With m
+     * sheets each step applies variance Delta^2/m, so that m steps make the
+     * whole filter (exponents add). */
+    const double Ls = p->L / (double)m;
+    const double d2 = p->filter_delta * p->filter_delta / (double)m;
     for (int q = 0; q < N; q++)
         for (int pp = 0; pp < N; pp++) {
             double fx = signed_index(pp, N) / (N * p->dx);
             double fy = signed_index(q, N) / (N * p->dx);
             size_t i = (size_t)q * N + pp;
             if (p->filter_delta > 0.0) {
-                double d2 = p->filter_delta * p->filter_delta;
                 H[2 * i] = exp(-2.0 * M_PI * M_PI * d2 * (fx * fx + fy * fy));
                 H[2 * i + 1] = 0.0;
             } else {
-                double ph = M_PI * p->lambda * p->L * (fx * fx + fy * fy);
+                double ph = M_PI * p->lambda * Ls * (fx * fx + fy * fy);
                 H[2 * i] = cos(ph);
                 H[2 * i + 1] = -sin(ph);
             }
@@ -348,39 +363,49 @@ int orc_run(const orc_params* p, double* E, double* Ninv, int n_trips,
     const double inv_nn = 1.0 / ((double)N * (double)N);
 
     for (int t = 0; t < n_trips; t++) {
-        double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
-        for (size_t i = 0; i < NN; i++) {
-            double er = E[2 * i], ei = E[2 * i + 1];
-            double I = er * er + ei * ei;            /* |E_n|^2 at the sheet */
-            double Nn = Ninv[i];
-            double a2 = A[2 * i] * A[2 * i] + A[2 * i + 1] * A[2 * i + 1];
-            double g = gain_amp(p, Nn, I);           /* gain sheet, amplitude */
-            s1 += I;
-            s2 += a2 * I;
-            s3 += a2 * g * g * I;
-            s4 += Nn;
-            /* local step f: G = sqrt(R) A g E_n (g = exp(N_n/2) for B class) */
-            double fr = sqR * g * er, fi = sqR * g * ei;
-            G[2 * i] = A[2 * i] * fr - A[2 * i + 1] * fi;
-            G[2 * i + 1] = A[2 * i] * fi + A[2 * i + 1] * fr;
-            /* inversion: relaxation toward the pump, depletion by |E_n|^2 */
-            Ninv[i] = inversion_next(p, Nn, P0[i], I);
+        for (int k = 0; k < m; k++) {
+            double* Nk = Ninv + (size_t)k * NN;      /* inversion of sheet k */
+            double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+            for (size_t i = 0; i < NN; i++) {
+                double er = E[2 * i], ei = E[2 * i + 1];
+                double I = er * er + ei * ei;        /* |E|^2 incident on the sheet */
+                double Nn = Nk[i];
+                double g = gain_amp(p, Nn, I);       /* gain sheet, amplitude */
+                if (k == 0) {
+                    /* the sheet at the mirror: local step f of Eq. (1),
+                     * G = sqrt(R) A g E_n (g = exp(N_n/2) for B class) */
+                    double a2 = A[2 * i] * A[2 * i] + A[2 * i + 1] * A[2 * i + 1];
+                    s1 += I;
+                    s2 += a2 * I;
+                    s3 += a2 * g * g * I;
+                    s4 += Nn;
+                    double fr = sqR * g * er, fi = sqR * g * ei;
+                    G[2 * i] = A[2 * i] * fr - A[2 * i + 1] * fi;
+                    G[2 * i + 1] = A[2 * i] * fi + A[2 * i + 1] * fr;
+                } else {
+                    /* a sheet away from the mirror: gain only */
+                    G[2 * i] = g * er;
+                    G[2 * i + 1] = g * ei;
+                }
+                /* inversion: relaxation toward the pump, depletion by |E|^2 */
+                Nk[i] = inversion_next(p, Nn, P0[i], I);
+            }
+            if (k == 0 && trace) {
+                trace[4 * (size_t)t + 0] = s1;
+                trace[4 * (size_t)t + 1] = s2;
+                trace[4 * (size_t)t + 2] = s3;
+                trace[4 * (size_t)t + 3] = s4;
+            }
+            /* nonlocal step to the next sheet: E <- IFFT2(H . FFT2(G)) */
+            if (orc_fft2(G, N, 0)) goto fail;
+            for (size_t i = 0; i < NN; i++) {
+                double gr = G[2 * i], gi = G[2 * i + 1];
+                G[2 * i] = gr * H[2 * i] - gi * H[2 * i + 1];
+                G[2 * i + 1] = gr * H[2 * i + 1] + gi * H[2 * i];
+            }
+            if (orc_fft2(G, N, 1)) goto fail;
+            for (size_t i = 0; i < 2 * NN; i++) E[i] = G[i] * inv_nn;
         }
-        if (trace) {
-            trace[4 * (size_t)t + 0] = s1;
-            trace[4 * (size_t)t + 1] = s2;
-            trace[4 * (size_t)t + 2] = s3;
-            trace[4 * (size_t)t + 3] = s4;
-        }
-        /* nonlocal step: E_{n+1} = IFFT2(H . FFT2(G)) */
-        if (orc_fft2(G, N, 0)) goto fail;
-        for (size_t i = 0; i < NN; i++) {
-            double gr = G[2 * i], gi = G[2 * i + 1];
-            G[2 * i] = gr * H[2 * i] - gi * H[2 * i + 1];
-            G[2 * i + 1] = gr * H[2 * i + 1] + gi * H[2 * i];
-        }
-        if (orc_fft2(G, N, 1)) goto fail;
-        for (size_t i = 0; i < 2 * NN; i++) E[i] = G[i] * inv_nn;
     }
     free(A); free(P0); free(H); free(G);
     return 0;

@@ -43,6 +43,12 @@ typedef struct {
                              trip with |E|^2 frozen
                            2 class-A laser, Eq. (8): saturable gain
                              N/(1 + T1|E|^2), inversion held at the pump     */
+    int    slices;      /* thin gain sheets per iterate, m; 0 or 1 = the single
+                           sheet of Eq. (1).  m > 1: the active medium cut
+                           into m thin sheets spread along the cavity, each
+                           holding its own inversion (the distributed-gain
+                           variant noted in Sec. 2.2 after Eq. (12)); see
+                           orc_run                                          */
 } orc_params;
 
 /* One-dimensional DFT of length n = 2^a 3^b, in place, unnormalized.
@@ -62,6 +68,12 @@ int  orc_dft_brute2d(const double* in, double* out, int n, int inverse);
 /* Advance (E, Ninv) by n_trips iterates of the round-trip map.
  * E: N*N complex field at the gain-sheet plane, before the local step.
  * Ninv: N*N inversion.  Both are updated in place.
+ * With m = slices > 1 an iterate is m steps, k = 0..m-1: thin sheet k with
+ * its own inversion (Ninv holds m*N*N values, sheet k at offset k*N*N),
+ * then free propagation over L/m (filter: variance Delta^2/m).  Sheet 0
+ * carries the mirror and aperture; every sheet has pump N0/m, so that the
+ * small-signal gain of an iterate is that of the single sheet.  The trace
+ * sums are those of sheet 0.
  * trace (nullable): 4*n_trips doubles; for trip t the raw sums
  *   [4t+0] S1 = sum |E_t|^2
  *   [4t+1] S2 = sum |A|^2 |E_t|^2

@@ -17,7 +17,8 @@ Recipe (used for every workload; the paper's cavity numbers are context only):
   sigma = 1e-3 (real and imaginary parts N(0, sigma^2/2)), drawn with NumPy's
   PCG64 generator seeded with 14102855 + cavity index; the oracle receives it
   as complex128, the GPU the same array rounded to complex64;
-* initial inversion N = N0 everywhere.
+* initial inversion N = N0 everywhere; with m thin gain sheets, N0/m on every
+  sheet (the inversion array is then m x N x N, sheet 0 at the mirror).
 """
 from __future__ import annotations
 
@@ -53,6 +54,7 @@ class Cavity:
     n0_override: float | None = None
     filter_delta: float = 0.0  # > 0: real renormalization-group filter (m) instead of Fresnel
     model: int = 0             # 0 B class (Euler update), 1 B class (exact update), 2 class A
+    slices: int = 1            # thin gain sheets per round trip
 
     @property
     def a(self) -> float:
@@ -90,8 +92,11 @@ def noise_field(N: int, index: int, sigma: float = NOISE_SIGMA) -> np.ndarray:
 
 
 def initial_state(cav: Cavity):
-    """(E0 complex128, Ninv0 float64) for a cavity."""
+    """(E0 complex128, Ninv0 float64) for a cavity; Ninv0 is (m, N, N) with
+    m > 1 gain sheets."""
     e = noise_field(cav.N, cav.index)
+    if cav.slices > 1:
+        return e, np.full((cav.slices, cav.N, cav.N), cav.N0 / cav.slices, dtype=np.float64)
     n = np.full((cav.N, cav.N), cav.N0, dtype=np.float64)
     return e, n
 
@@ -104,7 +109,7 @@ def oracle_params(cav: Cavity):
                         N0=cav.N0, T1=cav.T1, focal=cav.focal, ap_kind=cav.ap_kind,
                         ap_radius=cav.ap_radius, ap_order=cav.ap_order,
                         mod_amp=cav.mod_amp, mod_period=cav.mod_period,
-                        filter_delta=cav.filter_delta, model=cav.model)
+                        filter_delta=cav.filter_delta, model=cav.model, slices=cav.slices)
 
 
 # --------------------------------------------------------------------------

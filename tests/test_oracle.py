@@ -512,3 +512,111 @@ def test_propagate_composes_and_rejects_bad_distances():
     for bad in (-1e-3, float("nan"), float("inf")):
         with pytest.raises(ValueError):
             oracle.propagate(p, e0, bad)
+
+
+# ------------------------------------------------ several gain sheets ----
+
+@pytest.mark.parametrize("m,focal_over_L", [(3, math.inf), (4, 3.0)])
+def test_sheets_split_the_propagation_gaussian_beam(m, focal_over_L):
+    """With the gain off every sheet away from the mirror is the identity, so
+    m steps of L/m must give the one-sheet Gaussian-beam closed form of
+    Sec. 3, Eqs. (27)-(28): the mirror phase and the aperture act once, and
+    the distances add up to L."""
+    n = 256
+    lam, L = 1.064e-6, 2e-3
+    a = math.sqrt(100 * lam * L)
+    dx = 2 * a / n
+    Da = 0.07 * a
+    F = focal_over_L * L
+    p = passive(n, dx, lam, L, ap_kind=2, ap_radius=Da, focal=F, slices=m)
+    e, ninv, _ = oracle.run(p, np.ones((n, n)), np.zeros((m, n, n)), 1)
+    X, Y = grid(n, dx)
+    r2 = X ** 2 + Y ** 2
+    k = 2 * math.pi / lam
+    q = 1 + 1j / (k * Da ** 2 / L) + (0.0 if math.isinf(F) else L / F)
+    c = 1 / (2 * Da ** 2) - (0.0 if math.isinf(F) else 1j * k / (2 * F))
+    assert rel(e, np.exp(-c * r2 / q) / q) <= 1e-12
+    assert ninv.shape == (m, n, n) and not np.any(ninv)
+
+
+def test_sheets_split_the_filter_into_equal_variances():
+    """With the real filter of Eq. (18) and m sheets, the m filter steps
+    compose to the whole filter: a Gaussian exp(-r^2/a) spreads by the heat
+    kernel of variance Delta^2 exactly as with one sheet."""
+    n, dx, m = 256, 1e-5, 3
+    a = (12 * dx) ** 2
+    delta = 5 * dx
+    p = passive(n, dx, 1.064e-6, 2e-3, filter_delta=delta, slices=m)
+    X, Y = grid(n, dx)
+    r2 = X ** 2 + Y ** 2
+    e, _, _ = oracle.run(p, np.exp(-r2 / a), np.zeros((m, n, n)), 1)
+    b = a + 2 * delta ** 2
+    assert rel(e, a / b * np.exp(-r2 / b)) <= 1e-12
+
+
+def _sheet_fixed_point(R, P, T1, m):
+    """Stationary plane wave of m sheets, solved from the stationarity
+    conditions alone: sheet k sees intensity I_k, holds N_k = (P/m)/(1 + T1 I_k)
+    (relaxation balances depletion), multiplies the intensity by exp(N_k)
+    (times R at the mirror sheet 0), and the round trip closes:
+    ln R + sum N_k = 0."""
+    from scipy.optimize import brentq
+
+    def chain(I0):
+        I, Ns, Is = I0, [], []
+        for k in range(m):
+            Nk = (P / m) / (1 + T1 * I)
+            Ns.append(Nk)
+            Is.append(I)
+            I = I * math.exp(Nk) * (R if k == 0 else 1.0)
+        return Ns, Is
+
+    I0 = brentq(lambda I0: math.log(R) + sum(chain(I0)[0]), 1e-12, 10.0, xtol=1e-300, rtol=1e-15, maxiter=500)
+    return I0, chain(I0)
+
+
+@pytest.mark.parametrize("model", [0, 1, 2])
+def test_sheets_plane_wave_fixed_point(model):
+    """A uniform plane wave with no aperture stays put at the stationary
+    state of the m-sheet chain (its intensity changes from sheet to sheet,
+    so every sheet saturates differently).  The class-A sheets (model 2) hold
+    the pump P/m and saturate through the gain instead, with the same
+    intensities.  Pins the pump per sheet, the depleting intensity of each
+    sheet, and that the mirror acts at sheet 0."""
+    n, m, R, r, T1 = 8, 3, 0.9, 2.5, 400.0
+    P = r * math.log(1 / R)
+    p = CavityParams(N=n, dx=1e-5, lam=1.064e-6, L=2e-3, R=R, N0=P, T1=T1, ap_kind=0,
+                     model=model, slices=m)
+    I0, (Ns, Is) = _sheet_fixed_point(R, P, T1, m)
+    assert min(abs(Is[1] - Is[0]), abs(Is[2] - Is[1])) > 0.02 * Is[0]
+    e0 = np.full((n, n), math.sqrt(I0) * np.exp(0.4j))
+    held = [P / m] * m if model == 2 else Ns
+    n0 = np.stack([np.full((n, n), v) for v in held])
+    e, ninv, tr = oracle.run(p, e0, n0, 300)
+    assert np.max(np.abs(e - e0)) / math.sqrt(I0) <= 1e-11
+    assert np.max(np.abs(ninv - n0)) <= 1e-12
+    assert np.allclose(tr[:, 0], n * n * I0, rtol=1e-11)
+    assert np.allclose(tr[:, 3], n * n * held[0], rtol=1e-12)
+
+
+def test_sheets_relax_to_their_own_pump_without_field():
+    """E = 0: every sheet relaxes alone to the pump P/m by the linear
+    recursion N <- N + (P/m - N)/T1."""
+    n, m, T1, P = 8, 4, 20.0, 0.3
+    p = CavityParams(N=n, dx=1e-5, lam=1.064e-6, L=2e-3, R=0.9, N0=P, T1=T1, ap_kind=1,
+                     ap_radius=20e-5, slices=m)
+    start = np.random.default_rng(2).uniform(0.0, 0.2, (m, n, n))
+    _, ninv, _ = oracle.run(p, np.zeros((n, n)), start, 30)
+    assert np.max(np.abs(ninv - (P / m + (start - P / m) * (1 - 1 / T1) ** 30))) <= 1e-14
+
+
+def test_one_sheet_is_the_default_map_and_bad_counts_fail():
+    cav = dict(N=32, dx=1e-5, lam=1.064e-6, L=2e-3, R=0.9, N0=0.2, T1=100.0, ap_kind=1, ap_radius=10e-5)
+    e0 = rand_c((32, 32), 3) * 1e-3
+    n0 = np.full((32, 32), 0.2)
+    a = oracle.run(CavityParams(**cav), e0, n0, 3)
+    b = oracle.run(CavityParams(**cav, slices=1), e0, n0, 3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    with pytest.raises(ValueError):
+        oracle.run(CavityParams(**cav, slices=-1), e0, n0, 1)
