@@ -115,7 +115,8 @@ typedef struct {
  * stream to the null stream.  Tables are built in FP64 on the host and
  * uploaded once; no allocation happens in later calls except lsr_diag's
  * first use of its spectrum scratch and table replacement by
- * lsr_plan_set_gain / lsr_plan_set_filter / lsr_propagate. */
+ * lsr_plan_set_gain / lsr_plan_set_filter / lsr_plan_set_slices /
+ * lsr_propagate. */
 int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L,
                     double F, double R, const lsr_aperture* ap, lsr_prec prec);
 
@@ -160,6 +161,27 @@ int lsr_propagate(lsr_plan p, const void* E_in, double z, void* E_out);
  * their next call.  LSR_EINVAL for delta < 0 or non-finite. */
 int lsr_plan_set_filter(lsr_plan p, double delta);
 
+/* Several thin gain sheets per round trip: the active medium spread along
+ * the cavity instead of concentrated at one plane (the distributed-gain
+ * variant the paper notes in Sec. 2.2 after Eq. (12)).  With m > 1 sheets a
+ * round trip is m steps, k = 0..m-1: the local step of sheet k, then the
+ * nonlocal step over L/m (propagator table built in FP64 for L/m; the filter
+ * of lsr_plan_set_filter with variance delta^2/m, so that m steps make the
+ * whole filter).  Sheet 0 carries the mirror (R, curvature) and the aperture
+ * and holds the state E; the other sheets apply gain only.  Every sheet has
+ * its own inversion, pump N0/m (the round trip's small-signal gain stays that
+ * of one sheet), the plan's T1 and local-step model, and is depleted by the
+ * field incident on it.  m = 1 (default) is the single sheet of Eq. (1).
+ * After the call, lsr_roundtrips and lsr_time_kernels take Ninv as m*N*N
+ * values, sheet k at element offset k*N*N; lsr_diag reads sheet 0; the trace
+ * holds sheet 0's sums.  Launches: 2m per trip plus 1.  Waits for the plan's
+ * stream and allocates the table of the step (the previous one is freed).
+ * Batches run single-sheet plans only: lsr_batch_create and
+ * lsr_batch_roundtrips return LSR_EUNSUPPORTED for m > 1.
+ * LSR_EINVAL unless 1 <= m <= LSR_MAX_SLICES. */
+#define LSR_MAX_SLICES 64
+int lsr_plan_set_slices(lsr_plan p, int m);
+
 /* Pump and relaxation (Eq. (1), second line; periodic pump of Sec. 3):
  * N0(x,y) = N0 (1 + mod_amp cos(2 pi x/mod_period) cos(2 pi y/mod_period)),
  * uniform when mod_amp = 0 or mod_period = 0.  T1 > 0 in round trips. */
@@ -173,7 +195,8 @@ int lsr_plan_set_stream(lsr_plan p, void* hip_stream);
 /* Advance the state n_trips >= 0 round trips, in place, asynchronously.
  * E    device complex64 (complex128 for FP64 plans) N*N, row-major, the field
  *      at the gain sheet before the local step (E_n in, E_{n+n_trips} out).
- * Ninv device float (double for FP64 plans) N*N, row-major (N_n in, out).
+ * Ninv device float (double for FP64 plans) N*N, row-major (N_n in, out);
+ *      m*N*N (one map per sheet) after lsr_plan_set_slices(p, m).
  * Both must be 16-byte aligned and must not overlap.  During the call E's
  * memory also holds the transformed field in an internal tiled layout; it is
  * row-major again when the enqueued work completes.  Launches: 2 per trip

@@ -459,6 +459,8 @@ int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count) {
         if (plans[i]->device != plans[0]->device) return set_err(LSR_EINVAL, "plans on different devices");
         if (plans[i]->model != 0)
             return set_err(LSR_EUNSUPPORTED, "plan %d: batches run the default local step only", i);
+        if (plans[i]->slices != 1)
+            return set_err(LSR_EUNSUPPORTED, "plan %d: batches run single-sheet plans only", i);
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return set_err(LSR_EINVAL, "plan %d appears twice", i);
     }
@@ -543,6 +545,8 @@ int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* N, int n_trip
             return set_err(LSR_EINVAL, "state %zu: NULL or not 16-byte aligned", i);
         if (b->plans[i]->model != 0)
             return set_err(LSR_EUNSUPPORTED, "plan %zu: batches run the default local step only", i);
+        if (b->plans[i]->slices != 1)
+            return set_err(LSR_EUNSUPPORTED, "plan %zu: batches run single-sheet plans only", i);
     }
     if (n_trips == 0) return LSR_OK;
     DeviceGuard dg(b->device);

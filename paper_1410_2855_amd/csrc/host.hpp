@@ -55,6 +55,7 @@ struct lsr_plan_s {
     double N0 = 0, T1 = 1, mod_amp = 0, mod_period = 0;
     double filter = 0;                 // > 0: width of the real filter replacing the propagator
     int model = 0;                     // lsr_model
+    int slices = 1;                    // thin gain sheets per round trip
     unsigned version = 0;              // bumped whenever the descriptor d changes
     hipStream_t stream = nullptr;
     const lsr::Launchers* kern = nullptr;
@@ -66,6 +67,7 @@ struct lsr_plan_s {
     void* d_pump = nullptr;
     void* d_foc = nullptr;
     void* d_hz = nullptr;            // propagator table of the last lsr_propagate distance
+    void* d_hs = nullptr;            // nonlocal step between two of several gain sheets
     double* d_partials = nullptr;
     double* d_trace = nullptr;
     unsigned* d_counters = nullptr;

@@ -60,7 +60,10 @@ int launch_col_t(const CavDesc& d, int mode, hipStream_t st) {
         else hipLaunchKernelGGL((k_col<S, T, COL_PROP, PROP_TABLE>), g, b, 0, st, d);
         break;
     case COL_DIAG: hipLaunchKernelGGL((k_col<S, T, COL_DIAG, PROP_TABLE>), g, b, 0, st, d); break;
-    case COL_FREE: hipLaunchKernelGGL((k_col<S, T, COL_FREE, PROP_TABLE>), g, b, 0, st, d); break;
+    case COL_FREE:
+        if (d.prec == PREC_PLAIN && d.prop_kind == 0) hipLaunchKernelGGL((k_col<S, T, COL_FREE, PROP_PHASE>), g, b, 0, st, d);
+        else hipLaunchKernelGGL((k_col<S, T, COL_FREE, PROP_TABLE>), g, b, 0, st, d);
+        break;
     default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -3;

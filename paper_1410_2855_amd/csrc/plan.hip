@@ -151,7 +151,8 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 static void free_plan_memory(lsr_plan_s* p) {
     void* bufs[] = {p->d_tw, p->d_hx, p->d_pump, p->d_foc, p->d_partials, p->d_trace,
-                    p->d_counters, p->d_scratch, p->d_radial_part, p->d_diag_out, p->d_hz};
+                    p->d_counters, p->d_scratch, p->d_radial_part, p->d_diag_out, p->d_hz,
+                    p->d_hs};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -189,6 +190,62 @@ int launch_diag_reduce(const CavDesc& d, double* out, hipStream_t st) {
                        d.radial_part, d.nbins, out);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
+
+// Table of the nonlocal step between two of m > 1 gain sheets: the propagator
+// over L/m (FP64TAB, FP64) or the filter of variance delta^2/m, whose m steps
+// compose to the whole filter.  The plain Fresnel form evaluates its phase on
+// the device and has no table.
+static int build_sheet_table(const lsr_plan_s* p, int m, double filter, void** out) {
+    *out = nullptr;
+    if (m <= 1) return LSR_OK;
+    if (filter > 0) return upload(out, build_filter(p->N, p->dx, filter / std::sqrt((double)m)), p->prec != PREC_FP64);
+    if (p->prec == PREC_PLAIN) return LSR_OK;
+    return upload(out, build_hx(p->N, p->dx, p->lambda, p->L / m), p->prec != PREC_FP64);
+}
+
+// Descriptor of gain sheet k of the plan's m for a call on (E, Ninv).  Sheet 0
+// is the mirror plane (reflectivity, curvature, aperture); the others apply
+// gain only and hold their inversion k N^2 elements further on.  Every sheet
+// has pump N0/m and steps over L/m.
+static CavDesc sheet_desc(const lsr_plan_s* p, void* E, void* Ninv, int k) {
+    CavDesc d = p->d;
+    d.E = E;
+    d.Ninv = Ninv;
+    const int m = p->slices;
+    if (m == 1) return d;
+    d.hx = p->d_hs;
+    d.phase_c = p->d.phase_c / m;
+    d.N0 = p->d.N0 / m;
+    if (k > 0) {
+        d.Ninv = static_cast<char*>(Ninv) + (size_t)k * (size_t)p->N * (size_t)p->N * p->real_bytes();
+        d.sqrtR = 1.0;
+        d.ap_kind = AP_NONE;
+        d.mask = nullptr;
+        d.foc = nullptr;
+    }
+    return d;
+}
+
+// The launches of n >= 1 round trips, in order: the first row pass, then per
+// trip and sheet the column pass and the row pass of the next sheet; the last
+// row pass only finishes the inverse transform.  Sheet 0's column pass folds
+// the trip's sums into the trace ring, the other sheets' passes do not.
+// launch(desc, is_row, mode) returns 0 or a launcher error.
+template <class F>
+static int for_each_launch(const lsr_plan_s* p, void* E, void* Ninv, int n_trips, F&& launch) {
+    const int m = p->slices;
+    std::vector<CavDesc> sh((size_t)m);
+    for (int k = 0; k < m; ++k) sh[(size_t)k] = sheet_desc(p, E, Ninv, k);
+    int rc = launch(sh[0], true, ROW_FIRST);
+    for (int t = 0; t < n_trips && rc == 0; ++t)
+        for (int k = 0; k < m && rc == 0; ++k) {
+            rc = launch(sh[(size_t)k], false, k == 0 ? COL_PROP : COL_FREE);
+            const bool last = t + 1 == n_trips && k + 1 == m;
+            if (rc == 0) rc = launch(last ? sh[0] : sh[(size_t)((k + 1) % m)], true, last ? ROW_LAST : ROW_MID);
+        }
+    return rc;
+}
+
 }  // namespace lsr
 
 using namespace lsr;
@@ -379,15 +436,42 @@ int lsr_plan_set_filter(lsr_plan p, double delta) {
         int rc = upload(&t, build_hx(p->N, p->dx, p->lambda, p->L), p->prec != PREC_FP64);
         if (rc) return rc;
     }
-    if (p->d_hx) {
-        // the old table may still be read by enqueued work
-        LSR_HIP(hipStreamSynchronize(p->stream));
-        (void)hipFree(p->d_hx);
+    void* ts = nullptr;
+    int rc = build_sheet_table(p, p->slices, delta, &ts);
+    if (rc == LSR_OK && hipStreamSynchronize(p->stream) != hipSuccess)
+        rc = set_err(LSR_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(hipGetLastError()));
+    if (rc != LSR_OK) {
+        if (t) (void)hipFree(t);
+        if (ts) (void)hipFree(ts);
+        return rc;
     }
+    // the old tables are no longer read by enqueued work
+    if (p->d_hx) (void)hipFree(p->d_hx);
+    if (p->d_hs) (void)hipFree(p->d_hs);
     p->d_hx = t;
+    p->d_hs = ts;
     p->filter = delta;
     p->d.hx = t;
     p->d.prop_kind = delta > 0 ? 1 : 0;
+    ++p->version;
+    return LSR_OK;
+}
+
+int lsr_plan_set_slices(lsr_plan p, int m) {
+    if (!p) return set_err(LSR_EINVAL, "plan is NULL");
+    if (m < 1 || m > LSR_MAX_SLICES) return set_err(LSR_EINVAL, "%d gain sheets: must be 1..%d", m, LSR_MAX_SLICES);
+    DeviceGuard g(p->device);
+    void* ts = nullptr;
+    int rc = build_sheet_table(p, m, p->filter, &ts);
+    if (rc != LSR_OK) return rc;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) {
+        if (ts) (void)hipFree(ts);
+        return set_err(LSR_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    // the old table is no longer read by enqueued work
+    if (p->d_hs) (void)hipFree(p->d_hs);
+    p->d_hs = ts;
+    p->slices = m;
     ++p->version;
     return LSR_OK;
 }
@@ -410,15 +494,10 @@ int lsr_roundtrips(lsr_plan p, void* E, void* Ninv, int n_trips) {
     if (!aligned16(E) || !aligned16(Ninv)) return set_err(LSR_EINVAL, "E and Ninv must be 16-byte aligned");
     if (n_trips == 0) return LSR_OK;
     DeviceGuard g(p->device);
-    CavDesc d = p->d;
-    d.E = E;
-    d.Ninv = Ninv;
     const Launchers* k = p->kern;
-    int rc = k->row(d, ROW_FIRST, p->stream);
-    for (int t = 0; t < n_trips && rc == 0; ++t) {
-        rc = k->col(d, COL_PROP, p->stream);
-        if (rc == 0) rc = k->row(d, t + 1 < n_trips ? ROW_MID : ROW_LAST, p->stream);
-    }
+    const int rc = for_each_launch(p, E, Ninv, n_trips, [&](const CavDesc& d, bool row, int mode) {
+        return row ? k->row(d, mode, p->stream) : k->col(d, mode, p->stream);
+    });
     if (rc != 0) return set_err(LSR_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     p->trips_done += (unsigned long long)n_trips;
     p->last_n = n_trips;
@@ -430,11 +509,8 @@ int lsr_time_kernels(lsr_plan p, void* E, void* Ninv, int n_trips, double* ms) {
     if (n_trips < 1) return set_err(LSR_EINVAL, "n_trips < 1");
     if (!E || !Ninv || !aligned16(E) || !aligned16(Ninv)) return set_err(LSR_EINVAL, "bad E/Ninv pointer");
     DeviceGuard g(p->device);
-    CavDesc d = p->d;
-    d.E = E;
-    d.Ninv = Ninv;
     const Launchers* k = p->kern;
-    const int nl = 2 * n_trips + 1;
+    const int nl = 2 * n_trips * p->slices + 1;
     std::vector<hipEvent_t> ev(2 * (size_t)nl, nullptr);
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
@@ -442,29 +518,26 @@ int lsr_time_kernels(lsr_plan p, void* E, void* Ninv, int n_trips, double* ms) {
                 if (x) (void)hipEventDestroy(x);
             return set_err(LSR_EDEVICE, "hipEventCreate failed");
         }
-    int rc = 0, li = 0;
-    auto launch = [&](bool row, int mode) {
+    int li = 0;
+    int rc = for_each_launch(p, E, Ninv, n_trips, [&](const CavDesc& d, bool row, int mode) {
         (void)hipEventRecord(ev[2 * li], p->stream);
-        if (rc == 0) rc = row ? k->row(d, mode, p->stream) : k->col(d, mode, p->stream);
+        const int r = row ? k->row(d, mode, p->stream) : k->col(d, mode, p->stream);
         (void)hipEventRecord(ev[2 * li + 1], p->stream);
         ++li;
-    };
-    launch(true, ROW_FIRST);
-    for (int t = 0; t < n_trips; ++t) {
-        launch(false, COL_PROP);
-        launch(true, t + 1 < n_trips ? ROW_MID : ROW_LAST);
-    }
+        return r;
+    });
     double row_ms = 0, col_ms = 0;
     int nrow = 0, ncol = 0;
-    if (rc == 0 && hipStreamSynchronize(p->stream) == hipSuccess) {
-        // launch order: row, (col, row) * n; the first and last row launches
-        // (FIRST / LAST forms) are excluded from the row mean when n > 1
+    if (rc == 0 && li == nl && hipStreamSynchronize(p->stream) == hipSuccess) {
+        // launch order: row, (col, row) * n * m; the first and last row
+        // launches (FIRST / LAST forms) are excluded from the row mean unless
+        // they are the only ones
         for (int i = 0; i < nl; ++i) {
             float t = 0;
             (void)hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
             const bool row = (i % 2) == 0;
             if (row) {
-                if (n_trips > 1 && (i == 0 || i == nl - 1)) continue;
+                if (nl > 3 && (i == 0 || i == nl - 1)) continue;
                 row_ms += t;
                 ++nrow;
             } else {

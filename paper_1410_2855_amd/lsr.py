@@ -21,6 +21,7 @@ LSR_OK, LSR_EINVAL, LSR_ENOMEM, LSR_EDEVICE, LSR_EUNSUPPORTED, LSR_ENONFINITE = 
 LSR_PREC_PLAIN, LSR_PREC_FP64TAB, LSR_PREC_FP64 = 0, 1, 2
 LSR_AP_NONE, LSR_AP_SUPERGAUSS, LSR_AP_GAUSS, LSR_AP_MASK = 0, 1, 2, 3
 LSR_MODEL_B_EULER, LSR_MODEL_B_EXACT, LSR_MODEL_CLASS_A = 0, 1, 2
+LSR_MAX_SLICES = 64
 
 _STATUS = {0: "LSR_OK", -1: "LSR_EINVAL", -2: "LSR_ENOMEM", -3: "LSR_EDEVICE",
            -4: "LSR_EUNSUPPORTED", -5: "LSR_ENONFINITE"}
@@ -53,6 +54,7 @@ _SIGS = {
     "lsr_plan_set_gain": (_i, [_vp, _d, _d, _d, _d]),
     "lsr_plan_set_filter": (_i, [_vp, _d]),
     "lsr_plan_set_model": (_i, [_vp, _i]),
+    "lsr_plan_set_slices": (_i, [_vp, _i]),
     "lsr_propagate": (_i, [_vp, _vp, _d, _vp]),
     "lsr_plan_set_stream": (_i, [_vp, _vp]),
     "lsr_roundtrips": (_i, [_vp, _vp, _vp, _i]),
@@ -183,6 +185,10 @@ def lsr_plan_set_model(plan, model: int):
     _check(load().lsr_plan_set_model(plan, int(model)))
 
 
+def lsr_plan_set_slices(plan, m: int):
+    _check(load().lsr_plan_set_slices(plan, int(m)))
+
+
 def lsr_propagate(plan, E_in, z: float, E_out):
     _check(load().lsr_propagate(plan, _ptr(E_in), float(z), _ptr(E_out)))
 
@@ -305,6 +311,8 @@ class Plan:
             lsr_plan_set_filter(self.handle, cav.filter_delta)
         if getattr(cav, "model", 0):
             lsr_plan_set_model(self.handle, cav.model)
+        if getattr(cav, "slices", 1) != 1:
+            lsr_plan_set_slices(self.handle, cav.slices)
         lsr_plan_set_stream(self.handle, stream if stream is not None else torch.cuda.current_stream())
 
     @property
