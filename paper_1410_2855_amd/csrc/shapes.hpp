@@ -5,7 +5,7 @@
 // A "line" is one row (row pass) or one column (column pass) of the N x N
 // grid.  A line is transformed by L lanes, each holding P = N/L points in
 // registers; a workgroup handles LPW lines.  The same LPW is the edge of the
-// square tile of the internal field layout (see layout notes in kernels.hip):
+// square tile of the internal field layout (layout notes in map.hpp):
 // row-pass workgroups own LPW consecutive rows, column-pass workgroups LPW
 // consecutive columns, and every global access is a whole LPW x LPW tile.
 //
