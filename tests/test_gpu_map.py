@@ -207,8 +207,9 @@ def test_trace_records_each_trip_in_order():
     assert rel(np.vstack([tr1, tr2]), to) <= 1e-5
 
 
-def test_diag_matches_oracle_spectrum_and_sums():
-    cav = Cavity(N=512, F=150.0, R=0.9, pump_ratio=2.0, T1=1000.0, index=4)
+@pytest.mark.parametrize("N", [512, 4096])
+def test_diag_matches_oracle_spectrum_and_sums(N):
+    cav = Cavity(N=N, F=150.0 if N == 512 else 1000.0, R=0.9, pump_ratio=2.0, T1=1000.0, index=4)
     e0, n0 = initial_state(cav)
     rng = np.random.default_rng(0)
     n0 = n0 + 0.02 * rng.standard_normal(n0.shape)

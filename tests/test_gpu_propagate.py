@@ -46,6 +46,27 @@ def test_propagate_matches_oracle(N, prec, tol):
     p.close()
 
 
+def test_propagate_4096_out_of_place_and_in_place():
+    """4096^2 runs on workgroups that share tiles: the field is converted to
+    tiles and back around the transform, in E_out or in place."""
+    N = 4096
+    cav = Cavity(N=N, F=1000.0, R=0.9, pump_ratio=2.0, T1=1000.0, index=5, mod_amp=0.3, mod_periods=64)
+    e0, _ = initial_state(cav)
+    p = lsr.Plan(cav)
+    e, _ = p.state(e0, np.zeros((N, N)))
+    d = 2 * cav.a / cav.mod_periods
+    z = 2 * d * d / cav.lam / 3
+    out = p.propagate(e, z)
+    torch.cuda.synchronize()
+    assert rel(out.cpu().numpy(), oracle.propagate(oracle_params(cav), e0, z)) <= 2e-6
+    e_copy = e.clone()
+    lsr.lsr_propagate(p.handle, e, z, e)
+    p.sync()
+    assert torch.equal(e, out)
+    assert not torch.equal(e_copy, e)
+    p.close()
+
+
 def test_propagate_in_place_and_talbot_revival():
     """In place (E_in == E_out); a field of period d comes back at z_T."""
     N, M = 512, 16
