@@ -73,6 +73,44 @@ def test_long_run_1024_fp32_vs_fp64():
     stats_agree(p32, p64, s32, s64)
 
 
+def test_1024_fp32_phase_against_the_fp64_table():
+    """The 1024^2 workload in its two FP32 forms: the propagator phase
+    evaluated in FP32 on the device (plain) against the FP64-built table
+    reduced mod one turn.  The largest phase is pi N^2/(8F) = 1373 rad, so an
+    FP32 phase carries absolute errors of ~1e-4 rad at high frequencies.
+    After 50 trips both are compared with the FP64 oracle: over the whole
+    field they agree equally well (the energy sits at low frequencies, where
+    both phases are exact to FP32 rounding), while in the outer spectral band
+    the plain form is measurably worse (about 1.3x the table's error on this
+    workload).  The long run of the plain form is compared statistically with
+    the GPU FP64 form."""
+    cav = plain_1024()
+    e0, n0 = initial_state(cav)
+    eo, no, _ = oracle.run(oracle_params(cav), e0, n0, 50)
+    # the outer spectral band, where the phase is largest
+    f = np.abs(np.fft.fftfreq(cav.N) * cav.N)
+    band = (f[:, None] > cav.N / 4) | (f[None, :] > cav.N / 4)
+    fo = np.fft.fft2(eo)
+    err, berr = {}, {}
+    for prec in (lsr.LSR_PREC_PLAIN, lsr.LSR_PREC_FP64TAB):
+        p = lsr.Plan(cav, prec=prec)
+        e, n = p.state(e0, n0)
+        p.roundtrips(e, n, 50)
+        p.sync()
+        eg = e.cpu().numpy()
+        err[prec] = rel(eg, eo)
+        berr[prec] = rel(np.fft.fft2(eg)[band], fo[band])
+        p.close()
+    print("50 trips: rel L2 error plain %.3e, FP64 table %.3e; outer band plain %.3e, table %.3e"
+          % (err[lsr.LSR_PREC_PLAIN], err[lsr.LSR_PREC_FP64TAB], berr[lsr.LSR_PREC_PLAIN], berr[lsr.LSR_PREC_FP64TAB]))
+    assert err[lsr.LSR_PREC_FP64TAB] <= 1e-5 and err[lsr.LSR_PREC_PLAIN] <= 1e-5
+    assert berr[lsr.LSR_PREC_PLAIN] > berr[lsr.LSR_PREC_FP64TAB]
+    pp, sp = long_run(cav, lsr.LSR_PREC_PLAIN, 10000)
+    p64, s64 = long_run(cav, lsr.LSR_PREC_FP64, 10000)
+    assert np.all(np.isfinite(pp))
+    stats_agree(pp, p64, sp, s64)
+
+
 def test_long_run_2048_precision_form_vs_fp64():
     """2048^2, F=1000, R=0.9, pump 4x, T1=500, 20000 round trips."""
     cav = precision_2048()
