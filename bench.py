@@ -57,15 +57,22 @@ def load_traffic(kernel: str, pts_per_launch: int):
 
 # rocprofv3 commands whose output --summarize turns into the committed
 # summaries under profiles/ (run from /tmp with TMPDIR=/tmp; OUT is a scratch
-# output folder, /root/repo the repository)
+# output folder, /root/repo the repository); WL is empty for the metric's
+# workload, else "--workload NAME "
 PROFILE_COMMANDS = {
     "kernel_trace": "rocprofv3 --kernel-trace --stats --output-format csv -d OUT/kt -o kt -- "
-                    "python3 /root/repo/bench.py --steps 200 --warmup 20 --no-cpu-baseline --no-parity",
+                    "python3 /root/repo/bench.py WL--steps 200 --warmup 20 --no-cpu-baseline --no-parity",
     "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/pf -o pf -- "
-             "python3 /root/repo/bench.py --profile --steps 2 --warmup 1",
+             "python3 /root/repo/bench.py WL--profile --steps 2 --warmup 1",
     "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/pw -o pw -- "
-             "python3 /root/repo/bench.py --profile --steps 2 --warmup 1",
+             "python3 /root/repo/bench.py WL--profile --steps 2 --warmup 1",
 }
+
+
+def profile_commands(workload_flag: str = ""):
+    return {k: v.replace("WL", workload_flag) for k, v in PROFILE_COMMANDS.items()}
+
+
 PASS_KERNELS = {"row_pass": "lsr::k_pass<1, 0,", "column_pass": "lsr::k_pass<1, 1,"}
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 64 * 1024 * 1024 * 4   # the calibration copy of --profile, each way
@@ -78,9 +85,10 @@ def _read_csv(path):
         return list(csv.DictReader(f))
 
 
-def summarize(out_dir: str, workload: str, cavities: int, grid: int):
+def summarize(out_dir: str, workload: str, cavities: int, grid: int, workload_flag: str = ""):
     """Turn rocprofv3 csv output (OUT/kt, OUT/pf, OUT/pw of PROFILE_COMMANDS)
-    into text summaries and profiles/traffic.json.
+    into text summaries, and for the metric's workload (no workload flag)
+    profiles/traffic.json, which the bench line's roofline reads.
 
     HBM traffic per launch = FETCH_SIZE * (copy bytes / copy FETCH_SIZE) +
     WRITE_SIZE * (copy bytes / copy WRITE_SIZE): both counters are scaled by
@@ -105,8 +113,9 @@ def summarize(out_dir: str, workload: str, cavities: int, grid: int):
     algo = {"row_pass": ROW_BYTES_PER_PT * pts, "column_pass": COL_BYTES_PER_PT * pts}
     src = kernel_source_hash()
     traffic = {}
+    cmds = profile_commands(workload_flag)
     lines_all = ["rocprofv3 kernel statistics: %s" % workload, "",
-                 "command (from /tmp, TMPDIR=/tmp): " + PROFILE_COMMANDS["kernel_trace"], "",
+                 "command (from /tmp, TMPDIR=/tmp): " + cmds["kernel_trace"], "",
                  "%-12s %8s %12s %12s %12s  %s" % ("share %", "calls", "avg us", "min us", "max us", "kernel")]
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
         lines_all.append("%-12.2f %8s %12.2f %12.2f %12.2f  %s" % (
@@ -140,12 +149,13 @@ def summarize(out_dir: str, workload: str, cavities: int, grid: int):
                    write_kib, nw, scale["WRITE_SIZE"], wb / 2 ** 20),
                "HBM traffic per launch %.1f MiB = %.3f x algorithmic" % ((fb + wb) / 2 ** 20, (fb + wb) / algo[k]),
                "",
-               "commands (from /tmp, TMPDIR=/tmp):"] + ["  " + c for c in PROFILE_COMMANDS.values()] + [
+               "commands (from /tmp, TMPDIR=/tmp):"] + ["  " + c for c in cmds.values()] + [
                "kernel source hash: " + src]
         with open(os.path.join(prof, "%s_%dx%d.txt" % (k, cavities, grid)), "w") as f:
             f.write("\n".join(txt) + "\n")
-    with open(os.path.join(prof, "traffic.json"), "w") as f:
-        json.dump(traffic, f, indent=1)
+    if not workload_flag:
+        with open(os.path.join(prof, "traffic.json"), "w") as f:
+            json.dump(traffic, f, indent=1)
     print(json.dumps(traffic, indent=1))
 
 
@@ -157,6 +167,7 @@ WORKLOADS = {
 
 
 LOCAL_STEPS = {"b-euler": 0, "b-exact": 1, "class-a": 2}
+ENGINES = {0: "persistent", 1: "grouped", 2: "grouped-pipelined"}
 
 
 def make_workload(name: str, cavities: int):
@@ -230,8 +241,12 @@ def main():
                     help="write profiles/ summaries from rocprofv3 csv output under OUT (no GPU)")
     args = ap.parse_args()
     if args.summarize:
-        summarize(args.summarize, "%d cavities at 1024^2 (sweep parameter draws), FP64-table form"
-                  % args.cavities, args.cavities, 1024)
+        if args.workload == "sweep1024":
+            summarize(args.summarize, WORKLOADS["sweep1024"] % args.cavities, args.cavities, 1024)
+        elif args.workload == "structured4096":
+            summarize(args.summarize, WORKLOADS["structured4096"], 16, 4096, "--workload structured4096 ")
+        else:
+            sys.exit("--summarize covers the single-size workloads (sweep1024, structured4096)")
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: every cavity of the workload is independent and the "
@@ -329,7 +344,9 @@ def main():
     row_ms, col_ms, trip_ms = lsr.lsr_batch_time_kernels(batch, Es, Ns, 50)
     t_plain = timed(run_plain, max(1, args.steps // 4), max(1, args.warmup // 4))
     plain_value = pts / t_plain
-    if cfg["engine"] == 1:
+    if cfg["engine"] >= 1:
+        # grouped launches (engine 1, or its software-pipelined form 2): one
+        # kernel per pass
         kernels = {"row_pass": (row_ms, ROW_BYTES_PER_PT * pts), "column_pass": (col_ms, COL_BYTES_PER_PT * pts)}
     else:
         kernels = {"round_trip": (row_ms, TRIP_BYTES_PER_PT * pts)}
@@ -359,7 +376,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload,
                    "grid": sorted({c.N for c in cavs}), "cavities": len(cavs), "mode": "batched",
-                   "engine": "grouped" if cfg["engine"] == 1 else "persistent", "launch": cfg},
+                   "engine": ENGINES.get(cfg["engine"], "?"), "launch": cfg},
         "plain": {"value": plain_value, "ms_per_step": t_plain * 1e3},
         "speedup_batched_vs_plain": value / plain_value,
         "hbm_frac_whole_step": round(pts * TRIP_BYTES_PER_PT / t_step / 1e9 / HBM_PEAK_GBS, 4),
