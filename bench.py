@@ -216,6 +216,45 @@ def cpu_baseline(cavs, seconds_target: float = 12.0):
                                                       "/".join(str(n) for n in sorted({c.N for c in cavs[:cores]})))}
 
 
+def oracle_per_size(sizes=(256, 384, 512, 768, 1024, 2048, 4096), target_s: float = 1.5):
+    """Single-threaded oracle time per round trip at each grid size: the
+    median of three runs of k trips (k sized to about target_s per run; one
+    run includes the oracle's table set-up, amortised over its k trips).
+    Returns the host description and one record per size."""
+    import platform
+    import statistics
+
+    import oracle
+    from paper_1410_2855_amd.inputs import Cavity, initial_state, oracle_params
+
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    host = {"cpu": model or platform.processor(), "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)), "threads_used": 1}
+    rows = []
+    for N in sizes:
+        cav = Cavity(N=N, F=300.0, R=0.9, pump_ratio=2.0, T1=1000.0, index=1)
+        e0, n0 = initial_state(cav)
+        p = oracle_params(cav)
+        t0 = time.perf_counter()
+        oracle.run(p, e0, n0, 1)
+        one = time.perf_counter() - t0
+        k = max(1, int(target_s / max(one, 1e-4)))
+        runs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.run(p, e0, n0, k)
+            runs.append((time.perf_counter() - t0) / k)
+        t = statistics.median(runs)
+        rows.append({"N": N, "trips_per_run": k, "ms_per_trip": round(t * 1e3, 3),
+                     "grid_pts_round_trips_per_s": N * N / t})
+    return {"host": host, "per_size": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,7 +278,13 @@ def main():
                     help="short batched run for a profiler, plus a copy kernel of known size")
     ap.add_argument("--summarize", metavar="OUT",
                     help="write profiles/ summaries from rocprofv3 csv output under OUT (no GPU)")
+    ap.add_argument("--oracle-sizes", action="store_true",
+                    help="time the single-threaded FP64 oracle per round trip at every grid size "
+                         "(host only, no GPU) and print one JSON line")
     args = ap.parse_args()
+    if args.oracle_sizes:
+        print(json.dumps(oracle_per_size()), flush=True)
+        return
     if args.summarize:
         if args.workload == "sweep1024":
             summarize(args.summarize, WORKLOADS["sweep1024"] % args.cavities, args.cavities, 1024)
