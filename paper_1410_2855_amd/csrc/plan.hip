@@ -234,14 +234,12 @@ static CavDesc sheet_desc(const lsr_plan_s* p, void* E, void* Ninv, int k) {
 template <class F>
 static int for_each_launch(const lsr_plan_s* p, void* E, void* Ninv, int n_trips, F&& launch) {
     const int m = p->slices;
-    std::vector<CavDesc> sh((size_t)m);
-    for (int k = 0; k < m; ++k) sh[(size_t)k] = sheet_desc(p, E, Ninv, k);
-    int rc = launch(sh[0], true, ROW_FIRST);
+    int rc = launch(sheet_desc(p, E, Ninv, 0), true, ROW_FIRST);
     for (int t = 0; t < n_trips && rc == 0; ++t)
         for (int k = 0; k < m && rc == 0; ++k) {
-            rc = launch(sh[(size_t)k], false, k == 0 ? COL_PROP : COL_FREE);
+            rc = launch(sheet_desc(p, E, Ninv, k), false, k == 0 ? COL_PROP : COL_FREE);
             const bool last = t + 1 == n_trips && k + 1 == m;
-            if (rc == 0) rc = launch(last ? sh[0] : sh[(size_t)((k + 1) % m)], true, last ? ROW_LAST : ROW_MID);
+            if (rc == 0) rc = launch(sheet_desc(p, E, Ninv, last ? 0 : (k + 1) % m), true, last ? ROW_LAST : ROW_MID);
         }
     return rc;
 }
