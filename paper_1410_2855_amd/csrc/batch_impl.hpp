@@ -84,7 +84,11 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
                     // table) marks the cavity failed and releases its waiters
                     const unsigned need = (unsigned)d.nrb;
                     unsigned spins = 0;
-                    while (__hip_atomic_load(done + cav, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    // relaxed polls; the acquire fence after the loop pairs
+                    // with the row tasks' release increments (an acquire on
+                    // every poll would invalidate this XCD's L2 under the
+                    // row tasks still running on it)
+                    while (__hip_atomic_load(done + cav, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                         if (__hip_atomic_load(ctrl + CTRL_ABORT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
                         __builtin_amdgcn_s_sleep(2);
                         if (++spins > (1u << 25)) {   // ~2 s
