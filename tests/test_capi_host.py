@@ -44,6 +44,15 @@ def test_exports_every_declared_symbol():
     assert sorted(lsr.exported_symbols()) == names
 
 
+def test_binding_constants_match_the_header():
+    text = open(HEADER).read()
+    assert int(re.search(r"#define LSR_MAX_SLICES (\d+)", text).group(1)) == lsr.LSR_MAX_SLICES
+    for name in ("LSR_MODEL_B_EULER", "LSR_MODEL_B_EXACT", "LSR_MODEL_CLASS_A", "LSR_PREC_PLAIN",
+                 "LSR_PREC_FP64TAB", "LSR_PREC_FP64", "LSR_EINVAL", "LSR_EUNSUPPORTED", "LSR_ENONFINITE"):
+        m = re.search(name + r"\s*=\s*(-?\d+)", text)
+        assert m and int(m.group(1)) == getattr(lsr, name), name
+
+
 def test_version_and_registry():
     assert "gfx950" in lsr.lsr_version()
     for N in (256, 384, 512, 768, 1024, 2048, 4096):
