@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1410_2855_amd.inputs import initial_state, oracle_params, plain_1024, precision_2048, structured_4096
+from paper_1410_2855_amd.inputs import initial_state, oracle_params, plain_256, plain_1024, precision_2048, structured_4096
 
 pytestmark = pytest.mark.gpu
 
@@ -62,6 +62,31 @@ def stats_agree(p32, p64, s32, s64):
     assert abs(mean_a - mean_b) <= 0.01 * mean_b
     assert abs(rms_a - rms_b) <= 0.01 * mean_b
     assert dom_a == dom_b
+
+
+def test_long_run_256_against_the_oracle():
+    """The 256^2 workload (F=100, R=0.9, pump 2x, T1=1000), 300 round trips
+    against the FP64 CPU oracle itself: output-power statistics over the last
+    half and the dominant bin of the spectrum averaged at trips 200 and 300."""
+    cav = plain_256()
+    e0, n0 = initial_state(cav)
+    p = lsr.Plan(cav)
+    e, n = p.state(e0, n0)
+    pg, sg = [], np.zeros(lsr.lsr_plan_nbins(p.handle))
+    params = oracle_params(cav)
+    eo, no = e0, n0
+    po, so = [], np.zeros(oracle.nbins(cav.N))
+    for chunk in range(3):
+        p.roundtrips(e, n, 100)
+        pg.extend((1 - cav.R) * p.trace(100)[:, 2] * cav.dx ** 2)
+        eo, no, to = oracle.run(params, eo, no, 100)
+        po.extend((1 - cav.R) * to[:, 2] * cav.dx ** 2)
+        if chunk >= 1:
+            sg += p.diag(e, n)["radial"]
+            so += oracle.spectrum(params, eo, no)[0]
+    p.sync()
+    p.close()
+    stats_agree(np.asarray(pg), np.asarray(po), sg, so)
 
 
 def test_long_run_1024_fp32_vs_fp64():
