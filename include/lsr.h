@@ -265,10 +265,19 @@ int lsr_batch_set_graph_trips(lsr_batch b, int k);
  * in row tasks.  graph_k: trips per captured graph (0 = eager).  merge:
  * 0 = one kernel per grid size (each specialised for its size), 1 = cavities
  * of uneven grid sizes with the same workgroup size share one kernel (one
- * persistent launch per trip covers them all).  cfg_out (nullable) receives
- * the resulting seven values in this order. */
+ * persistent launch per trip covers them all).  shape: FFT plan of the
+ * one-size groups (merge = 0): 0 = each size's default plan (the one-cavity
+ * path's), k = 1 .. LSR_MAX_SHAPES = alternative plan k of the sizes that
+ * have one compiled (others keep their default):
+ *   1  reversed radix order: 512 as 16 8 4, 1024 as 16 16 4, 2048 as 16 16 8;
+ *   2  1024 on 8 x 8 tiles, eight lines per workgroup.
+ * Every plan computes the same transform; with an alternative plan the
+ * batch's results differ from the one-cavity path's only by rounding (they
+ * are bitwise equal with shape 0).  cfg_out (nullable) receives the
+ * resulting eight values in this order. */
+#define LSR_MAX_SHAPES 2
 int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, int chunk,
-                        int lag, int graph_k, int merge, int* cfg_out);
+                        int lag, int graph_k, int merge, int shape, int* cfg_out);
 
 /* Profiling form of lsr_batch_roundtrips (eager, no graph): each pass is
  * launched with HIP events that the dispatch itself timestamps at kernel
@@ -283,11 +292,13 @@ int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* Ninv, int n
 
 void lsr_batch_destroy(lsr_batch b);
 
-/* Autotune: time the candidate launch shapes of plan p (and/or of batch b)
- * on the device with scratch state, keep the fastest, and store it in the
- * JSON cache at cache_path (NULL = $LSR_TUNE_CACHE or no file).  The winner
- * applies to the plan/batch at once and to later plans/batches of the same
- * sizes and precision.  Synchronises. */
+/* Autotune: time the candidate configurations of batch b (lsr_batch_configure:
+ * FFT plan, engine, register budget, grouping, persistent-kernel chunk, lag
+ * and residency, graph length) on the device with scratch state, keep the
+ * fastest, and store it in the JSON cache at cache_path (NULL =
+ * $LSR_TUNE_CACHE or no file).  The winner applies to the batch at once and
+ * to later batches of the same sizes.  A plan alone (b = NULL) has a single
+ * compiled plan per size and nothing to choose.  Synchronises. */
 int lsr_autotune(lsr_plan p, lsr_batch b, const char* cache_path);
 
 /* ---------------------------------------------------------------------- */

@@ -22,11 +22,16 @@ GroupInfo group_1024();
 GroupInfo group_2048();
 GroupInfo group_4096();
 GroupInfo group_small();
+GroupInfo group_512r();
+GroupInfo group_1024r();
+GroupInfo group_1024t();
+GroupInfo group_2048r();
 
 static const std::vector<GroupInfo>& groups() {
     static const std::vector<GroupInfo> g = {group_256(),  group_384(),  group_512(),
                                              group_768(),  group_1024(), group_2048(),
-                                             group_4096(), group_small()};
+                                             group_4096(), group_small(), group_512r(),
+                                             group_1024r(), group_1024t(), group_2048r()};
     return g;
 }
 int group_count() { return (int)groups().size(); }
@@ -81,6 +86,8 @@ struct Tune {
     int graph_k = 16;     // trips per captured graph; 0 = eager
     int merge = 0;        // 0 one group (kernel) per grid size; 1 one group per
                           // workgroup size, uneven sizes sharing one kernel
+    int shape = 0;        // FFT plan of single-size groups: 0 the size's default,
+                          // k > 0 its alternative plan k where one is compiled
 };
 
 // --------------------------------------------------------------- cache ----
@@ -125,6 +132,7 @@ static std::map<std::string, Tune> cache_read(const std::string& path) {
         get("lag", t.lag);
         get("graph_k", t.graph_k);
         get("merge", t.merge);
+        get("shape", t.shape);
         m[key] = t;
         i = cb + 1;
     }
@@ -141,9 +149,9 @@ static bool cache_write(const std::string& path, const std::map<std::string, Tun
     for (const auto& kv : m) {
         fprintf(f,
                 "  \"%s\": {\"engine\": %d, \"variant\": %d, \"wgs_per_cu\": %d, \"chunk\": %d, \"lag\": %d, "
-                "\"graph_k\": %d, \"merge\": %d}%s\n",
+                "\"graph_k\": %d, \"merge\": %d, \"shape\": %d}%s\n",
                 kv.first.c_str(), kv.second.engine, kv.second.variant, kv.second.wgs_per_cu, kv.second.chunk,
-                kv.second.lag, kv.second.graph_k, kv.second.merge, ++n < m.size() ? "," : "");
+                kv.second.lag, kv.second.graph_k, kv.second.merge, kv.second.shape, ++n < m.size() ? "," : "");
     }
     fprintf(f, "}\n");
     fclose(f);
@@ -165,6 +173,7 @@ struct BatchGroup {
     int4* d_cols = nullptr;          // column tasks only (grouped column pass)
     int ncols = 0;
     unsigned* d_ctrl = nullptr;
+    void* d_tw = nullptr;            // twiddles of an alternative plan (else the plans' own)
     int occ[4] = {1, 1, 1, 1};   // resident workgroups per CU of each variant
     int occ_pipe[4][2] = {};     // same for the pipelined row / column pass
 };
@@ -192,6 +201,7 @@ static void groups_free(lsr_batch_s* b) {
         if (g.d_last) (void)hipFree(g.d_last);
         if (g.d_cols) (void)hipFree(g.d_cols);
         if (g.d_ctrl) (void)hipFree(g.d_ctrl);
+        if (g.d_tw) (void)hipFree(g.d_tw);
     }
     b->grp.clear();
     b->lastE.clear();
@@ -214,12 +224,19 @@ static std::string batch_key(const std::vector<lsr_plan>& plans) {
     return k;
 }
 
+// Row (= column) blocks of a size-N cavity under its group's FFT plan.
+static int group_blocks(const BatchGroup& g, int N) {
+    for (int k = 0; k < g.g->nsizes; ++k)
+        if (g.g->sizes[k] == N) return N / g.g->shapes[k].LPW;
+    return 0;
+}
+
 // (Re)build the task lists of every group for the current tuning.
 static int batch_pack(lsr_batch_s* b) {
     const int lag = b->tune.lag >= 0 ? b->tune.lag : default_lag();
     for (auto& g : b->grp) {
         std::vector<int> nrb;
-        for (int c : g.cav) nrb.push_back(b->plans[c]->d.nrb);
+        for (int c : g.cav) nrb.push_back(group_blocks(g, b->plans[c]->N));
         std::vector<int4> t, l, cols;
         pack(nrb, lag, true, t);
         pack(nrb, 0, false, l);
@@ -244,10 +261,12 @@ static int batch_pack(lsr_batch_s* b) {
 }
 
 // Cavities -> groups.  merge = 0: one group per grid size (each kernel
-// specialised for its size: registers and LDS of that size only); merge = 1:
-// one group per workgroup size, the smallest compiled kernel that covers all
-// the part's sizes (uneven sizes advance in one launch).  Allocates the
-// groups' descriptor and control blocks and packs their task lists.
+// specialised for its size: registers and LDS of that size only), with the
+// size's alternative FFT plan tune.shape where one is compiled; merge = 1:
+// one group per workgroup size, the smallest compiled kernel of default plans
+// that covers all the part's sizes (uneven sizes advance in one launch).
+// Allocates the groups' descriptor and control blocks (and the twiddles of an
+// alternative plan) and packs their task lists.
 static int batch_partition(lsr_batch_s* b) {
     groups_free(b);
     std::map<int, std::vector<int>> parts;
@@ -258,9 +277,13 @@ static int batch_partition(lsr_batch_s* b) {
     }
     for (auto& kv : parts) {
         const GroupInfo* best = nullptr;
+        const int want = b->tune.merge ? 0 : b->tune.shape;
+        for (int pass = 0; pass < 2 && !best; ++pass)
         for (int gi = 0; gi < group_count() && !best; ++gi) {
             const GroupInfo* g = group_at(gi);
             if (b->tune.merge ? g->threads != kv.first : (g->nsizes != 1 || g->sizes[0] != kv.first)) continue;
+            // the wanted plan first, else the default one
+            if (g->alt != (pass == 0 ? want : 0)) continue;
             bool all = true;
             for (int c : kv.second) {
                 bool in = false;
@@ -286,6 +309,14 @@ static int batch_partition(lsr_batch_s* b) {
         if (hipMalloc(&g.d_desc, ncav * sizeof(CavDesc)) != hipSuccess ||
             hipMalloc(&g.d_ctrl, (CTRL_ROWDONE + ncav) * sizeof(unsigned)) != hipSuccess)
             return set_err(LSR_ENOMEM, "batch allocation failed");
+        if (best->alt != 0) {
+            // twiddles of the alternative plan, FP64-built like a plan's own
+            const std::vector<double> tw = build_twiddles(best->shapes[0], false, true);
+            std::vector<float> twf(tw.begin(), tw.end());
+            if (hipMalloc(&g.d_tw, twf.size() * sizeof(float)) != hipSuccess)
+                return set_err(LSR_ENOMEM, "batch allocation failed");
+            LSR_HIP(hipMemcpy(g.d_tw, twf.data(), twf.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
         std::vector<unsigned> ctrl(CTRL_ROWDONE + ncav, 0u);
         ctrl[CTRL_NCAV] = (unsigned)ncav;
         if (hipMemcpy(g.d_ctrl, ctrl.data(), ctrl.size() * sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess)
@@ -394,6 +425,8 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
             CavDesc d = b->plans[c]->d;
             d.E = E[c];
             d.Ninv = N[c];
+            if (g.d_tw) d.tw = g.d_tw;
+            d.nrb = group_blocks(g, d.N);
             h.push_back(d);
         }
         LSR_HIP(hipMemcpyAsync(g.d_desc, h.data(), h.size() * sizeof(CavDesc), hipMemcpyHostToDevice, b->stream));
@@ -502,9 +535,9 @@ int lsr_batch_set_graph_trips(lsr_batch b, int k) {
 }
 
 int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, int chunk, int lag, int graph_k,
-                        int merge, int* cfg_out) {
+                        int merge, int shape, int* cfg_out) {
     if (!b) return set_err(LSR_EINVAL, "batch is NULL");
-    if (engine > 2 || variant > 3 || chunk == 0 || chunk > 1024 || merge > 1)
+    if (engine > 2 || variant > 3 || chunk == 0 || chunk > 1024 || merge > 1 || shape > LSR_MAX_SHAPES)
         return set_err(LSR_EINVAL, "bad batch configuration");
     DeviceGuard dg(b->device);
     Tune t = b->tune;
@@ -515,7 +548,8 @@ int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, in
     if (lag >= 0) t.lag = lag;
     if (graph_k >= 0) t.graph_k = graph_k;
     if (merge >= 0) t.merge = merge;
-    const bool regroup = t.merge != b->tune.merge;
+    if (shape >= 0) t.shape = shape;
+    const bool regroup = t.merge != b->tune.merge || t.shape != b->tune.shape;
     const bool repack = t.lag != b->tune.lag;
     drop_graph(b);
     b->tune = t;
@@ -532,6 +566,7 @@ int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, in
         cfg_out[4] = t.lag >= 0 ? t.lag : default_lag();
         cfg_out[5] = t.graph_k;
         cfg_out[6] = t.merge;
+        cfg_out[7] = t.shape;
     }
     return LSR_OK;
 }
@@ -707,9 +742,19 @@ int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
             best = b->tune;
         }
     };
-    for (int mg = 0; mg <= (mixed ? 1 : 0); ++mg) {
+    // alternative FFT plans compiled for some size of the batch
+    int max_alt = 0;
+    for (int gi = 0; gi < group_count(); ++gi) {
+        const GroupInfo* g = group_at(gi);
+        if (g->alt == 0 || g->nsizes != 1) continue;
+        for (auto* q : b->plans)
+            if (q->N == g->sizes[0]) max_alt = std::max(max_alt, g->alt);
+    }
+    for (int mg = 0; mg <= (mixed ? 1 : 0); ++mg)
+    for (int sh = 0; sh <= (mg ? 0 : max_alt); ++sh) {
         b->tune = saved;
         b->tune.merge = mg;
+        b->tune.shape = sh;
         if (batch_partition(b)) continue;
         const Tune base = b->tune;
         int nvar = 1;
@@ -724,7 +769,8 @@ int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
                 t.graph_k = 16;
                 consider(t, trips);
             }
-        for (int v = 0; v < nvar; ++v) {
+        // persistent-kernel settings for the default plans only
+        for (int v = 0; v < (sh == 0 ? nvar : 0); ++v) {
             int occ = 1;
             for (auto& g : b->grp) occ = std::max(occ, g.occ[v < g.g->nvariants ? v : 0]);
             std::vector<int> wgs;
@@ -743,7 +789,7 @@ int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
                     }
         }
     }
-    if (best.merge != b->tune.merge) {
+    if (best.merge != b->tune.merge || best.shape != b->tune.shape) {
         b->tune = best;
         if (batch_partition(b)) {
             release();

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "desc.hpp"
+#include "shapes.hpp"
 
 namespace lsr {
 
@@ -38,6 +39,8 @@ struct GroupInfo {
     int threads;
     int nsizes;
     int sizes[8];
+    ShapeInfo shapes[8];   // the FFT plan of each size
+    int alt;               // 0: the sizes' default plans; k > 0: alternative plan k
     int nvariants;
     KernelVariant var[4];
 };

@@ -341,11 +341,12 @@ struct GroupKernels {
 };
 
 template <class... Ss>
-GroupInfo group_info(std::initializer_list<KernelVariant> vars) {
+GroupInfo group_info(std::initializer_list<KernelVariant> vars, int alt = 0) {
     GroupInfo gi{};
     gi.threads = Group<Ss...>::THREADS;
+    gi.alt = alt;
     gi.nsizes = 0;
-    ((gi.sizes[gi.nsizes++] = Ss::N), ...);
+    ((gi.shapes[gi.nsizes] = shape_info<Ss>(), gi.sizes[gi.nsizes++] = Ss::N), ...);
     gi.nvariants = 0;
     for (const KernelVariant& v : vars) gi.var[gi.nvariants++] = v;
     return gi;

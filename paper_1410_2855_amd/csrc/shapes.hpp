@@ -99,6 +99,14 @@ using S768  = Shape<768, 64, 4, 12, 4, 4, 4>;
 using S1024 = Shape<1024, 64, 4, 4, 16, 16>;
 using S2048 = Shape<2048, 128, 4, 8, 16, 16>;
 using S4096 = Shape<4096, 256, 4, 16, 16, 16>;
+// Alternative plans for batches, chosen per grid size by the autotuner: the
+// same transform with another radix order (r) or with 8 x 8 tiles of eight
+// lines per workgroup (t).  Each pass is a whole 1D DFT in natural order, so
+// only the twiddle table and the tile edge go with the choice.
+using S512r  = Shape<512, 32, 8, 16, 8, 4>;
+using S1024r = Shape<1024, 64, 4, 16, 16, 4>;
+using S1024t = Shape<1024, 64, 8, 4, 16, 16>;
+using S2048r = Shape<2048, 128, 4, 16, 16, 8>;
 // FP64 complex field (16 B/point): half the lines per workgroup.
 using D256  = Shape<256, 16, 8, 16, 16>;
 using D384  = Shape<384, 16, 8, 8, 12, 4>;
@@ -109,6 +117,7 @@ using D2048 = Shape<2048, 64, 2, 8, 16, 16>;
 
 static_assert(S256::valid() && S384::valid() && S512::valid() && S768::valid() &&
               S1024::valid() && S2048::valid() && S4096::valid(), "bad fp32 shape");
+static_assert(S512r::valid() && S1024r::valid() && S1024t::valid() && S2048r::valid(), "bad alternative shape");
 static_assert(D256::valid() && D384::valid() && D512::valid() && D768::valid() &&
               D1024::valid() && D2048::valid(), "bad fp64 shape");
 

@@ -22,6 +22,7 @@ LSR_PREC_PLAIN, LSR_PREC_FP64TAB, LSR_PREC_FP64 = 0, 1, 2
 LSR_AP_NONE, LSR_AP_SUPERGAUSS, LSR_AP_GAUSS, LSR_AP_MASK = 0, 1, 2, 3
 LSR_MODEL_B_EULER, LSR_MODEL_B_EXACT, LSR_MODEL_CLASS_A = 0, 1, 2
 LSR_MAX_SLICES = 64
+LSR_MAX_SHAPES = 2
 
 _STATUS = {0: "LSR_OK", -1: "LSR_EINVAL", -2: "LSR_ENOMEM", -3: "LSR_EDEVICE",
            -4: "LSR_EUNSUPPORTED", -5: "LSR_ENONFINITE"}
@@ -68,7 +69,7 @@ _SIGS = {
     "lsr_batch_roundtrips": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i]),
     "lsr_batch_diag": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(lsr_diag_out)]),
     "lsr_batch_set_graph_trips": (_i, [_vp, _i]),
-    "lsr_batch_configure": (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, ctypes.POINTER(_i)]),
+    "lsr_batch_configure": (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _i, ctypes.POINTER(_i)]),
     "lsr_batch_time_kernels": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, ctypes.POINTER(_d)]),
     "lsr_batch_destroy": (None, [_vp]),
     "lsr_autotune": (_i, [_vp, _vp, ctypes.c_char_p]),
@@ -268,10 +269,10 @@ def lsr_batch_set_graph_trips(batch, k: int):
 
 
 def lsr_batch_configure(batch, engine=-1, variant=-1, wgs_per_cu=-1, chunk=-1, lag=-1, graph_k=-1,
-                        merge=-1) -> dict:
-    out = (ctypes.c_int * 7)()
-    _check(load().lsr_batch_configure(batch, engine, variant, wgs_per_cu, chunk, lag, graph_k, merge, out))
-    return dict(zip(("engine", "variant", "wgs_per_cu", "chunk", "lag", "graph_k", "merge"), out[:]))
+                        merge=-1, shape=-1) -> dict:
+    out = (ctypes.c_int * 8)()
+    _check(load().lsr_batch_configure(batch, engine, variant, wgs_per_cu, chunk, lag, graph_k, merge, shape, out))
+    return dict(zip(("engine", "variant", "wgs_per_cu", "chunk", "lag", "graph_k", "merge", "shape"), out[:]))
 
 
 def lsr_batch_time_kernels(batch, Es, Ns, n_trips: int):

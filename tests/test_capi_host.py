@@ -47,6 +47,7 @@ def test_exports_every_declared_symbol():
 def test_binding_constants_match_the_header():
     text = open(HEADER).read()
     assert int(re.search(r"#define LSR_MAX_SLICES (\d+)", text).group(1)) == lsr.LSR_MAX_SLICES
+    assert int(re.search(r"#define LSR_MAX_SHAPES (\d+)", text).group(1)) == lsr.LSR_MAX_SHAPES
     for name in ("LSR_MODEL_B_EULER", "LSR_MODEL_B_EXACT", "LSR_MODEL_CLASS_A", "LSR_PREC_PLAIN",
                  "LSR_PREC_FP64TAB", "LSR_PREC_FP64", "LSR_EINVAL", "LSR_EUNSUPPORTED", "LSR_ENONFINITE"):
         m = re.search(name + r"\s*=\s*(-?\d+)", text)

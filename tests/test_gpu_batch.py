@@ -48,6 +48,17 @@ def mixed(count, sizes):
     return cavs
 
 
+def assert_matches_plain(cfg, Es, Ns, ref):
+    """Bitwise the one-cavity path with the default FFT plans; to rounding
+    (FP32, a few trips) with an alternative plan."""
+    for i in range(len(ref)):
+        if cfg["shape"] == 0:
+            assert torch.equal(Es[i], ref[i][0]) and torch.equal(Ns[i], ref[i][1]), i
+        else:
+            assert rel(Es[i].cpu().numpy(), ref[i][0].cpu().numpy()) <= 2e-6, i
+            assert rel(Ns[i].cpu().numpy(), ref[i][1].cpu().numpy()) <= 2e-6, i
+
+
 @pytest.mark.parametrize("sizes,count,trips,k,engine,merge", [
     ((256, 384, 512, 768, 1024), 9, 13, 4, 2, 1),  # one kernel for all sizes, graph + remainder
     ((256, 384, 512, 768, 1024), 9, 13, 4, 1, 0),  # one kernel per size
@@ -143,11 +154,10 @@ def test_autotune_writes_cache_and_keeps_results(tmp_path):
     path = str(tmp_path / "tune.json")
     lsr.lsr_autotune(None, b, path)
     text = open(path).read()
-    assert "gfx950:batch:512x3;" in text
+    assert "gfx950:batch:512x3;" in text and '"shape"' in text
     lsr.lsr_batch_roundtrips(b, Es, Ns, 9)
     ref, _ = plain_reference(cavs, 9)
-    for i in range(len(cavs)):
-        assert torch.equal(Es[i], ref[i][0]) and torch.equal(Ns[i], ref[i][1])
+    assert_matches_plain(lsr.lsr_batch_configure(b), Es, Ns, ref)
     lsr.lsr_batch_destroy(b)
     for p in plans:
         p.close()
@@ -155,8 +165,8 @@ def test_autotune_writes_cache_and_keeps_results(tmp_path):
 
 def test_autotune_mixed_sizes_keeps_results(tmp_path):
     """A batch whose grid sizes share a workgroup size: the tuner also times
-    the merged kernel; whatever it picks, the results stay bitwise those of
-    the one-cavity path."""
+    the merged kernel and the alternative FFT plans; whatever it picks, the
+    results stay those of the one-cavity path (bitwise with default plans)."""
     cavs = mixed(4, (256, 512))
     plans, Es, Ns = make(cavs)
     b = lsr.lsr_batch_create([p.handle for p in plans])
@@ -167,8 +177,7 @@ def test_autotune_mixed_sizes_keeps_results(tmp_path):
     assert cfg["merge"] in (0, 1)
     lsr.lsr_batch_roundtrips(b, Es, Ns, 9)
     ref, _ = plain_reference(cavs, 9)
-    for i in range(len(cavs)):
-        assert torch.equal(Es[i], ref[i][0]) and torch.equal(Ns[i], ref[i][1])
+    assert_matches_plain(cfg, Es, Ns, ref)
     lsr.lsr_batch_destroy(b)
     for p in plans:
         p.close()
@@ -216,6 +225,53 @@ def test_batch_follows_new_state_buffers_between_calls():
         assert torch.equal(Es2[i], ref[i][0]) and torch.equal(Ns2[i], ref[i][1])
         # the first buffers were left alone by the second call
         assert torch.equal(Es[i], keep[i][0]) and torch.equal(Ns[i], keep[i][1])
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
+
+
+@pytest.mark.parametrize("N,shape", [(512, 1), (1024, 1), (1024, 2), (2048, 1)])
+@pytest.mark.parametrize("engine", [1, 0, 2])
+def test_alternative_fft_plans(N, shape, engine):
+    """The batch's alternative FFT plans (another radix order, or 8 x 8 tiles)
+    compute the same map: 50 trips against the FP64 oracle to the usual bar,
+    a few trips against the one-cavity path to FP32 rounding, and every
+    engine bitwise equal to the grouped one on the same plan."""
+    cavs = [c.with_(N=N) for c in sweep(3, seed=11, sizes=(N,))]
+    trips = 50 if engine == 1 else 6
+    results = {}
+    for eng in sorted({1, engine}):
+        plans, Es, Ns = make(cavs)
+        b = lsr.lsr_batch_create([p.handle for p in plans])
+        cfg = lsr.lsr_batch_configure(b, engine=eng, shape=shape, graph_k=4)
+        assert cfg["shape"] == shape
+        lsr.lsr_batch_roundtrips(b, Es, Ns, trips)
+        for p in plans:
+            p.sync()
+        results[eng] = [(e.clone(), n.clone()) for e, n in zip(Es, Ns)]
+        tr = [p.trace(trips) for p in plans]
+        lsr.lsr_batch_destroy(b)
+        for p in plans:
+            p.close()
+    if engine != 1:
+        for (e1, n1), (e2, n2) in zip(results[1], results[engine]):
+            assert torch.equal(e1, e2) and torch.equal(n1, n2)
+        return
+    eo, no, to = oracle.run(oracle_params(cavs[0]), *initial_state(cavs[0]), trips)
+    e, n = results[1][0]
+    assert rel(e.cpu().numpy(), eo) <= 1e-5 and rel(n.cpu().numpy(), no) <= 1e-5
+    assert rel(tr[0], to) <= 1e-5
+    ref, _ = plain_reference(cavs, 3)
+    plans, Es, Ns = make(cavs)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    cfg = lsr.lsr_batch_configure(b, engine=1, shape=shape)
+    lsr.lsr_batch_roundtrips(b, Es, Ns, 3)
+    for p in plans:
+        p.sync()
+    assert_matches_plain(cfg, Es, Ns, ref)
+    with pytest.raises(lsr.LsrError) as ei:
+        lsr.lsr_batch_configure(b, shape=lsr.LSR_MAX_SHAPES + 1)
+    assert ei.value.code == lsr.LSR_EINVAL
     lsr.lsr_batch_destroy(b)
     for p in plans:
         p.close()
