@@ -229,13 +229,15 @@ int lsr_plan_nbins(lsr_plan p);
 void lsr_plan_destroy(lsr_plan p);
 
 /* ---------------------------------------------------------------------- */
-/* Batching: many cavities of uneven N and parameters advanced together by */
-/* one persistent kernel per round trip, replayed as a HIP graph of k      */
-/* round trips.  Only LSR_PREC_FP64TAB plans can be batched.              */
+/* Batching: many cavities of uneven N and parameters advanced together,  */
+/* by one grouped launch per pass or one persistent kernel per round trip, */
+/* replayed as a HIP graph of k round trips.  Batches take                 */
+/* LSR_PREC_FP64TAB plans with the default local step and one gain sheet.  */
 /* ---------------------------------------------------------------------- */
 
-/* Build a batch over count >= 1 plans (borrowed).  The task table, the
- * launch shape and k come from the autotune cache when it holds an entry
+/* Build a batch over count >= 1 plans (borrowed).  The launch
+ * configuration (FFT plan, engine, register budget, grouping, task-table
+ * lag, graph length k) comes from the autotune cache when it holds an entry
  * for this mix of sizes, else from built-in defaults.  The batch runs on
  * the stream of plans[0]. */
 int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count);
