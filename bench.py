@@ -266,8 +266,8 @@ def main():
                          "parameter draws; sweep512: 512 cavities of N in {256..1024}; structured4096: "
                          "16 cavities at 4096^2 with the periodic pump")
     ap.add_argument("--local-step", choices=sorted(LOCAL_STEPS), default="b-euler",
-                    help="local step of the map; other than b-euler the cavities run one launch sequence "
-                         "each (batches run the default local step only)")
+                    help="local step of the map (b-euler: Eq. (1); b-exact: the rate equation solved over "
+                         "a trip; class-a: the saturable gain of the class-A laser)")
     ap.add_argument("--filter-delta", type=float, default=0.0,
                     help="> 0: the renormalization-group filter of this width, in grid spacings, "
                          "replaces the Fresnel step")
@@ -329,31 +329,6 @@ def main():
     def run_plain(k):
         for p, e, n in zip(plans, Es, Ns):
             p.roundtrips(e, n, k)
-
-    if model:
-        # one launch sequence per cavity; kernel times from the first cavity
-        run_plain(args.warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run_plain(args.steps)
-        torch.cuda.synchronize()
-        t = (time.perf_counter() - t0) / args.steps
-        rms, cms = lsr.lsr_time_kernels(plans[0].handle, Es[0], Ns[0], 20)
-        p0 = cavs[0].N ** 2
-        for p in plans:
-            p.sync()
-        print(json.dumps({
-            "metric": "grid-pts x round-trips/s (one launch sequence per cavity)", "value": pts / t,
-            "unit": "grid-pts*round-trips/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "c64", "data": "synthetic",
-            "config": {"workload": workload, "cavities": len(cavs), "mode": "plain"},
-            "kernels_first_cavity_ms": {"row_pass": rms, "column_pass": cms,
-                                        "row_GBps": ROW_BYTES_PER_PT * p0 / (rms * 1e-3) / 1e9,
-                                        "column_GBps": COL_BYTES_PER_PT * p0 / (cms * 1e-3) / 1e9}}), flush=True)
-        for p in plans:
-            p.close()
-        return
 
     batch = lsr.lsr_batch_create([p.handle for p in plans])
     if args.autotune:

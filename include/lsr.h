@@ -132,9 +132,10 @@ int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L,
  *                    exp(N / (2 (1 + T1 I))); the inversion state follows the
  *                    pump, N' = P.
  * The trace and diagnostics sums use the model's gain factor in place of
- * exp(N).  Takes effect on the next call.  Batches run the default model
- * only: lsr_batch_create and lsr_batch_roundtrips return LSR_EUNSUPPORTED for
- * a plan with another model.  LSR_EINVAL for an unknown model. */
+ * exp(N).  Takes effect on the next call, also in batches holding the plan
+ * (a batch regroups its cavities when a model changes: sizes with a cavity
+ * of another model run on kernels that read each cavity's model).
+ * LSR_EINVAL for an unknown model. */
 typedef enum { LSR_MODEL_B_EULER = 0, LSR_MODEL_B_EXACT = 1, LSR_MODEL_CLASS_A = 2 } lsr_model;
 int lsr_plan_set_model(lsr_plan p, int model);
 
@@ -232,7 +233,7 @@ void lsr_plan_destroy(lsr_plan p);
 /* Batching: many cavities of uneven N and parameters advanced together,  */
 /* by one grouped launch per pass or one persistent kernel per round trip, */
 /* replayed as a HIP graph of k round trips.  Batches take                 */
-/* LSR_PREC_FP64TAB plans with the default local step and one gain sheet.  */
+/* LSR_PREC_FP64TAB plans of one gain sheet, any local-step model.         */
 /* ---------------------------------------------------------------------- */
 
 /* Build a batch over count >= 1 plans (borrowed).  The launch

@@ -26,12 +26,22 @@ GroupInfo group_512r();
 GroupInfo group_1024r();
 GroupInfo group_1024t();
 GroupInfo group_2048r();
+GroupInfo group_any_256();
+GroupInfo group_any_384();
+GroupInfo group_any_512();
+GroupInfo group_any_768();
+GroupInfo group_any_1024();
+GroupInfo group_any_2048();
+GroupInfo group_any_4096();
 
 static const std::vector<GroupInfo>& groups() {
     static const std::vector<GroupInfo> g = {group_256(),  group_384(),  group_512(),
                                              group_768(),  group_1024(), group_2048(),
                                              group_4096(), group_small(), group_512r(),
-                                             group_1024r(), group_1024t(), group_2048r()};
+                                             group_1024r(), group_1024t(), group_2048r(),
+                                             group_any_256(), group_any_384(), group_any_512(),
+                                             group_any_768(), group_any_1024(), group_any_2048(),
+                                             group_any_4096()};
     return g;
 }
 int group_count() { return (int)groups().size(); }
@@ -188,6 +198,7 @@ struct lsr_batch_s {
     std::vector<BatchGroup> grp;
     std::vector<void*> lastE, lastN;
     std::vector<unsigned> lastVer;   // plan descriptor versions of the last upload
+    std::vector<int> models;         // the plans' local-step models when grouped
     Tune tune;
     std::string key;
     hipGraphExec_t graph = nullptr;
@@ -269,19 +280,32 @@ static int batch_pack(lsr_batch_s* b) {
 // alternative plan) and packs their task lists.
 static int batch_partition(lsr_batch_s* b) {
     groups_free(b);
+    // sizes with a cavity of another local-step model than the default run
+    // on kernels that read each cavity's model (key -N, one group per size)
+    b->models.clear();
+    std::map<int, bool> other_model;
+    for (auto* q : b->plans) {
+        b->models.push_back(q->model);
+        other_model[q->N] = other_model[q->N] || q->model != 0;
+    }
     std::map<int, std::vector<int>> parts;
     for (int i = 0; i < (int)b->plans.size(); ++i) {
         ShapeInfo s;
         shape_for(b->plans[i]->N, false, &s);
-        parts[b->tune.merge ? s.threads : b->plans[i]->N].push_back(i);
+        const int N = b->plans[i]->N;
+        parts[other_model[N] ? -N : b->tune.merge ? s.threads : N].push_back(i);
     }
     for (auto& kv : parts) {
         const GroupInfo* best = nullptr;
-        const int want = b->tune.merge ? 0 : b->tune.shape;
+        const bool any = kv.first < 0;
+        const bool merged = b->tune.merge && !any;
+        const int key = any ? -kv.first : kv.first;
+        const int want = (merged || any) ? 0 : b->tune.shape;
         for (int pass = 0; pass < 2 && !best; ++pass)
         for (int gi = 0; gi < group_count() && !best; ++gi) {
             const GroupInfo* g = group_at(gi);
-            if (b->tune.merge ? g->threads != kv.first : (g->nsizes != 1 || g->sizes[0] != kv.first)) continue;
+            if (g->any_model != (any ? 1 : 0)) continue;
+            if (merged ? g->threads != key : (g->nsizes != 1 || g->sizes[0] != key)) continue;
             // the wanted plan first, else the default one
             if (g->alt != (pass == 0 ? want : 0)) continue;
             bool all = true;
@@ -439,6 +463,17 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
     return LSR_OK;
 }
 
+// A plan's local-step model changed since the batch was grouped: regroup
+// (the kernels of a group read the models it was built for).
+static int regroup_if_models_changed(lsr_batch_s* b) {
+    bool same = b->models.size() == b->plans.size();
+    for (size_t i = 0; same && i < b->plans.size(); ++i) same = b->models[i] == b->plans[i]->model;
+    if (same) return LSR_OK;
+    LSR_HIP(hipStreamSynchronize(b->stream));
+    drop_graph(b);
+    return batch_partition(b);
+}
+
 static int run_trips(lsr_batch_s* b, int n) {
     int rc = launch_trip(b, ROW_FIRST);
     int left = n - 1;
@@ -490,8 +525,6 @@ int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count) {
         if (plans[i]->prec != PREC_FP64TAB)
             return set_err(LSR_EUNSUPPORTED, "only FP64TAB plans (FP32 field, FP64-built tables) can be batched");
         if (plans[i]->device != plans[0]->device) return set_err(LSR_EINVAL, "plans on different devices");
-        if (plans[i]->model != 0)
-            return set_err(LSR_EUNSUPPORTED, "plan %d: batches run the default local step only", i);
         if (plans[i]->slices != 1)
             return set_err(LSR_EUNSUPPORTED, "plan %d: batches run single-sheet plans only", i);
         for (int j = 0; j < i; ++j)
@@ -578,8 +611,6 @@ int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* N, int n_trip
     for (size_t i = 0; i < b->plans.size(); ++i) {
         if (!E[i] || !N[i] || ((uintptr_t)E[i] & 15u) || ((uintptr_t)N[i] & 15u))
             return set_err(LSR_EINVAL, "state %zu: NULL or not 16-byte aligned", i);
-        if (b->plans[i]->model != 0)
-            return set_err(LSR_EUNSUPPORTED, "plan %zu: batches run the default local step only", i);
         if (b->plans[i]->slices != 1)
             return set_err(LSR_EUNSUPPORTED, "plan %zu: batches run single-sheet plans only", i);
     }
@@ -588,7 +619,8 @@ int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* N, int n_trip
     // order after the caller's work on the plans' stream, and back
     LSR_HIP(hipEventRecord(b->ev_in, b->user));
     LSR_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
-    int rc = upload_descs(b, E, N, false);
+    int rc = regroup_if_models_changed(b);
+    if (rc == LSR_OK) rc = upload_descs(b, E, N, false);
     if (rc == LSR_OK) rc = run_trips(b, n_trips);
     LSR_HIP(hipEventRecord(b->ev_out, b->stream));
     LSR_HIP(hipStreamWaitEvent(b->user, b->ev_out, 0));
@@ -606,7 +638,8 @@ int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* N, int n_tr
     DeviceGuard dg(b->device);
     LSR_HIP(hipEventRecord(b->ev_in, b->user));
     LSR_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
-    int rc = upload_descs(b, E, N, false);
+    int rc = regroup_if_models_changed(b);
+    if (rc == LSR_OK) rc = upload_descs(b, E, N, false);
     if (rc) return rc;
     // dispatch timestamps of trip t: row pass (or persistent trip kernel)
     // start/stop = events 4t, 4t+1; column pass start/stop = 4t+2, 4t+3

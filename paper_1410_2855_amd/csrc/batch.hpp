@@ -41,6 +41,7 @@ struct GroupInfo {
     int sizes[8];
     ShapeInfo shapes[8];   // the FFT plan of each size
     int alt;               // 0: the sizes' default plans; k > 0: alternative plan k
+    int any_model;         // 1: each cavity's own local-step model; 0: the default one
     int nvariants;
     KernelVariant var[4];
 };

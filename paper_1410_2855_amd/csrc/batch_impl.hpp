@@ -45,18 +45,31 @@ struct Group {
     }
 };
 
-template <int MODE, class S>
+// ANY = 0: the default local step, compiled in; ANY = 1: the cavity's own
+// local-step model (d.model, uniform in a workgroup), one compiled body each.
+template <int MODE, int ANY, class S>
 __device__ __forceinline__ bool run_if(const CavDesc& d, int kind, int blk, unsigned char* smem, double* red) {
     if (d.N != S::N) return false;
     cx<float>* lds = reinterpret_cast<cx<float>*>(smem);
-    if (kind == TASK_ROW) row_task<S, float, MODE>(d, blk, lds, red);
-    else col_task<S, float, COL_PROP>(d, blk, lds);
+    if (kind == TASK_ROW) {
+        if constexpr (ANY && MODE != ROW_LAST) {
+            switch (d.model) {
+            case 1: row_task<S, float, MODE, 1>(d, blk, lds, red); break;
+            case 2: row_task<S, float, MODE, 2>(d, blk, lds, red); break;
+            default: row_task<S, float, MODE, 0>(d, blk, lds, red); break;
+            }
+        } else {
+            row_task<S, float, MODE>(d, blk, lds, red);
+        }
+    } else {
+        col_task<S, float, COL_PROP>(d, blk, lds);
+    }
     return true;
 }
 
 // WPE: waves per SIMD the register allocation must allow (2 leaves 256
 // VGPRs, 3 leaves 168); the autotuner picks the faster variant.
-template <int MODE, int THREADS, int LDS_BYTES, int WPE, class... Ss>
+template <int MODE, int THREADS, int LDS_BYTES, int WPE, int ANY, class... Ss>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_trip(const CavDesc* __restrict__ descs,
                                                   const int4* __restrict__ tasks, int ntasks,
                                                   unsigned* __restrict__ ctrl, int chunk) {
@@ -104,7 +117,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
                 __syncthreads();
                 if (blk == 0 && threadIdx.x < 64) finalize_sums(d);
             }
-            (run_if<MODE, Ss>(d, kind, blk, smem, red) || ...);
+            (run_if<MODE, ANY, Ss>(d, kind, blk, smem, red) || ...);
             if (kind == TASK_ROW) {
                 // each wave waits for its stores to reach L2; after the
                 // barrier one device-scope release writes the XCD's L2 back
@@ -150,7 +163,7 @@ __device__ __forceinline__ void col_task_hx_lds(const CavDesc& d, int cb, unsign
                                                                lds + S::LDS_ELEMS);
 }
 
-template <int MODE, int KIND, int THREADS, int LDS_BYTES, int WPE, class... Ss>
+template <int MODE, int KIND, int THREADS, int LDS_BYTES, int WPE, int ANY, class... Ss>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_pass(
     const CavDesc* __restrict__ descs, const int4* __restrict__ tasks) {
     constexpr bool HXLDS = sizeof...(Ss) == 1 && KIND == TASK_COL &&
@@ -171,7 +184,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
         if (blk == 0 && threadIdx.x < 64) finalize_sums(d);
     }
     if constexpr (HXLDS) (col_task_hx_lds<Ss>(d, blk, smem), ...);
-    else (run_if<MODE, Ss>(d, KIND, blk, smem, red) || ...);
+    else (run_if<MODE, ANY, Ss>(d, KIND, blk, smem, red) || ...);
 }
 
 // Software-pipelined grouped pass for a single grid size: a resident grid
@@ -255,28 +268,30 @@ constexpr bool pipe_fits() {
             hipLaunchKernelGGL(KERN, G, B, 0, ST, __VA_ARGS__);                             \
     } while (0)
 
-template <int WPE, class... Ss>
-struct GroupKernels {
+// ANY = 1: kernels that run each cavity's own local-step model (groups for
+// batches holding other models than the default; no pipelined form).
+template <int WPE, int ANY, class... Ss>
+struct GroupKernelsT {
     static constexpr int THREADS = Group<Ss...>::THREADS;
     static constexpr int LDS = Group<Ss...>::maxl();
     // the pipelined pass exists for single-size groups whose LDS (lines,
     // twiddles, propagator table) fits one workgroup
-    static constexpr bool PIPE = pipe_fits<Ss...>();
+    static constexpr bool PIPE = !ANY && pipe_fits<Ss...>();
 
     static int launch(int mode, int grid, hipStream_t st, const CavDesc* descs, const int4* tasks,
                       int ntasks, unsigned* ctrl, int chunk, LaunchEvents ev) {
         const dim3 g(grid), b(THREADS);
         switch (mode) {
-        case ROW_FIRST: LSR_LAUNCH((k_trip<ROW_FIRST, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks, ntasks, ctrl, chunk); break;
-        case ROW_MID:   LSR_LAUNCH((k_trip<ROW_MID, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks, ntasks, ctrl, chunk); break;
-        case ROW_LAST:  LSR_LAUNCH((k_trip<ROW_LAST, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks, ntasks, ctrl, chunk); break;
+        case ROW_FIRST: LSR_LAUNCH((k_trip<ROW_FIRST, THREADS, LDS, WPE, ANY, Ss...>), g, b, st, ev, descs, tasks, ntasks, ctrl, chunk); break;
+        case ROW_MID:   LSR_LAUNCH((k_trip<ROW_MID, THREADS, LDS, WPE, ANY, Ss...>), g, b, st, ev, descs, tasks, ntasks, ctrl, chunk); break;
+        case ROW_LAST:  LSR_LAUNCH((k_trip<ROW_LAST, THREADS, LDS, WPE, ANY, Ss...>), g, b, st, ev, descs, tasks, ntasks, ctrl, chunk); break;
         default: return -1;
         }
         return hipGetLastError() == hipSuccess ? 0 : -3;
     }
     static int occupancy() {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trip<ROW_MID, THREADS, LDS, WPE, Ss...>, THREADS, 0) != hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_trip<ROW_MID, THREADS, LDS, WPE, ANY, Ss...>, THREADS, 0) != hipSuccess)
             return 1;
         return n > 0 ? n : 1;
     }
@@ -285,12 +300,12 @@ struct GroupKernels {
                            int ntasks, LaunchEvents ev) {
         const dim3 g(ntasks), b(THREADS);
         if (kind == TASK_COL) {
-            LSR_LAUNCH((k_pass<ROW_MID, TASK_COL, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks);
+            LSR_LAUNCH((k_pass<ROW_MID, TASK_COL, THREADS, LDS, WPE, ANY, Ss...>), g, b, st, ev, descs, tasks);
         } else {
             switch (mode) {
-            case ROW_FIRST: LSR_LAUNCH((k_pass<ROW_FIRST, TASK_ROW, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks); break;
-            case ROW_MID:   LSR_LAUNCH((k_pass<ROW_MID, TASK_ROW, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks); break;
-            case ROW_LAST:  LSR_LAUNCH((k_pass<ROW_LAST, TASK_ROW, THREADS, LDS, WPE, Ss...>), g, b, st, ev, descs, tasks); break;
+            case ROW_FIRST: LSR_LAUNCH((k_pass<ROW_FIRST, TASK_ROW, THREADS, LDS, WPE, ANY, Ss...>), g, b, st, ev, descs, tasks); break;
+            case ROW_MID:   LSR_LAUNCH((k_pass<ROW_MID, TASK_ROW, THREADS, LDS, WPE, ANY, Ss...>), g, b, st, ev, descs, tasks); break;
+            case ROW_LAST:  LSR_LAUNCH((k_pass<ROW_LAST, TASK_ROW, THREADS, LDS, WPE, ANY, Ss...>), g, b, st, ev, descs, tasks); break;
             default: return -1;
             }
         }
@@ -340,11 +355,15 @@ struct GroupKernels {
     }
 };
 
+template <int WPE, class... Ss>
+using GroupKernels = GroupKernelsT<WPE, 0, Ss...>;
+
 template <class... Ss>
-GroupInfo group_info(std::initializer_list<KernelVariant> vars, int alt = 0) {
+GroupInfo group_info(std::initializer_list<KernelVariant> vars, int alt = 0, int any_model = 0) {
     GroupInfo gi{};
     gi.threads = Group<Ss...>::THREADS;
     gi.alt = alt;
+    gi.any_model = any_model;
     gi.nsizes = 0;
     ((gi.shapes[gi.nsizes] = shape_info<Ss>(), gi.sizes[gi.nsizes++] = Ss::N), ...);
     gi.nvariants = 0;

@@ -70,19 +70,61 @@ def test_models_one_trip_every_size():
             assert rel(eg, eo) <= 1e-6 and rel(ng, no) <= 1e-6, (N, model)
 
 
-def test_batches_refuse_other_models():
-    cavs = sweep(2, seed=1, sizes=(512,))
+@pytest.mark.parametrize("engine", [1, 0, 2])
+def test_batches_run_every_model(engine):
+    """A batch of cavities with all three local steps (and two grid sizes, one
+    of them default-only) is bitwise the one-cavity path per cavity, and
+    follows a model changed between calls."""
+    cavs = [c.with_(model=m) for c, m in zip(sweep(6, seed=1, sizes=(512, 1024)), (0, 1, 2, 0, 1, 2))]
+    cavs += [c.with_(N=256, index=40 + i) for i, c in enumerate(sweep(2, seed=4, sizes=(256,)))]
+
+    def run(batched):
+        plans = [lsr.Plan(c) for c in cavs]
+        st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+        Es, Ns = [x[0] for x in st], [x[1] for x in st]
+        b = None
+        if batched:
+            b = lsr.lsr_batch_create([p.handle for p in plans])
+            lsr.lsr_batch_configure(b, engine=engine, graph_k=2)
+
+        def go(k):
+            if batched:
+                lsr.lsr_batch_roundtrips(b, Es, Ns, k)
+            else:
+                for p, e, n in zip(plans, Es, Ns):
+                    p.roundtrips(e, n, k)
+
+        go(5)
+        lsr.lsr_plan_set_model(plans[0].handle, lsr.LSR_MODEL_CLASS_A)   # a 512 cavity
+        lsr.lsr_plan_set_model(plans[6].handle, lsr.LSR_MODEL_B_EXACT)   # the 256 size joins in
+        go(4)
+        for p in plans:
+            p.sync()
+        out = [(e.clone(), n.clone()) for e, n in zip(Es, Ns)]
+        if b:
+            lsr.lsr_batch_destroy(b)
+        for p in plans:
+            p.close()
+        return out
+
+    ref = run(False)
+    got = run(True)
+    for i, ((e1, n1), (e2, n2)) in enumerate(zip(ref, got)):
+        assert torch.equal(e1, e2) and torch.equal(n1, n2), i
+
+
+def test_batched_models_match_the_oracle():
+    cavs = [c.with_(model=m) for c, m in zip(sweep(3, seed=2, sizes=(512,)), (0, 1, 2))]
     plans = [lsr.Plan(c) for c in cavs]
     st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
     b = lsr.lsr_batch_create([p.handle for p in plans])
-    lsr.lsr_plan_set_model(plans[1].handle, lsr.LSR_MODEL_CLASS_A)
-    with pytest.raises(lsr.LsrError) as ei:
-        lsr.lsr_batch_roundtrips(b, [s[0] for s in st], [s[1] for s in st], 2)
-    assert ei.value.code == lsr.LSR_EUNSUPPORTED
+    lsr.lsr_batch_roundtrips(b, [x[0] for x in st], [x[1] for x in st], 50)
+    for p in plans:
+        p.sync()
+    for c, (e, n) in zip(cavs, st):
+        eo, no, _ = oracle.run(oracle_params(c), *initial_state(c), 50)
+        assert rel(e.cpu().numpy(), eo) <= 1e-5 and rel(n.cpu().numpy(), no) <= 1e-5, c.model
     lsr.lsr_batch_destroy(b)
-    with pytest.raises(lsr.LsrError) as ei:
-        lsr.lsr_batch_create([p.handle for p in plans])
-    assert ei.value.code == lsr.LSR_EUNSUPPORTED
     with pytest.raises(lsr.LsrError) as ei:
         lsr.lsr_plan_set_model(plans[0].handle, 7)
     assert ei.value.code == lsr.LSR_EINVAL
