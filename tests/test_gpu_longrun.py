@@ -12,7 +12,8 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1410_2855_amd.inputs import initial_state, oracle_params, plain_256, plain_1024, precision_2048, structured_4096
+from paper_1410_2855_amd.inputs import (initial_state, oracle_params, plain_256, plain_1024, precision_2048,
+                                        structured_4096, sweep)
 
 pytestmark = pytest.mark.gpu
 
@@ -87,6 +88,34 @@ def test_long_run_256_against_the_oracle():
     p.sync()
     p.close()
     stats_agree(np.asarray(pg), np.asarray(po), sg, so)
+
+
+def test_long_run_batched_sweep_vs_fp64():
+    """The batched sweep's cavities (uneven N, F, pump, T1, R), 5000 round trips
+    batched in the FP32 form against each cavity alone in the GPU FP64 form:
+    power statistics over the last half and the dominant bin of the spectrum
+    averaged every 100 trips, for the first 64 cavities of the sweep."""
+    trips, every = 5000, 100
+    cavs = sweep(512)[:64]
+    plans = [lsr.Plan(c) for c in cavs]
+    st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+    Es, Ns = [x[0] for x in st], [x[1] for x in st]
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    power = [[] for _ in cavs]
+    spec = [np.zeros(lsr.lsr_plan_nbins(p.handle)) for p in plans]
+    for k in range(trips // every):
+        lsr.lsr_batch_roundtrips(b, Es, Ns, every)
+        for i, (p, c) in enumerate(zip(plans, cavs)):
+            power[i].extend((1 - c.R) * p.trace(every)[:, 2] * c.dx ** 2)
+            if (k + 1) * every > trips // 2:
+                spec[i] += lsr.lsr_batch_diag(b, i, Es[i], Ns[i], spec[i].size)["radial"]
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.sync()
+        p.close()
+    for i, c in enumerate(cavs):
+        p64, s64 = long_run(c, lsr.LSR_PREC_FP64, trips, chunk=trips, spec_every=every)
+        stats_agree(np.asarray(power[i]), p64, spec[i], s64)
 
 
 def test_long_run_1024_fp32_vs_fp64():
