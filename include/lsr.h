@@ -104,7 +104,7 @@ typedef struct {
 
 /* Create a plan for one cavity.
  * N      grid points per side; supported: 256, 384, 512, 768, 1024, 2048, 4096
- *        (LSR_EUNSUPPORTED otherwise; FP64 plans up to 2048).
+ *        (LSR_EUNSUPPORTED otherwise), in every precision form.
  * dx     grid spacing (m) > 0; lambda wavelength (m) > 0; L propagation length
  *        of one iterate (m) >= 0.  The Fresnel number is (N dx/2)^2/(lambda L).
  * F      mirror focal length (m) of the curvature phase exp(i k r^2/(2F)) of

@@ -4,9 +4,8 @@
 namespace lsr {
 
 #define LSR_DECL(n) const Launchers* launchers_##n##f(); const Launchers* launchers_##n##d();
-LSR_DECL(256) LSR_DECL(384) LSR_DECL(512) LSR_DECL(768) LSR_DECL(1024) LSR_DECL(2048)
+LSR_DECL(256) LSR_DECL(384) LSR_DECL(512) LSR_DECL(768) LSR_DECL(1024) LSR_DECL(2048) LSR_DECL(4096)
 #undef LSR_DECL
-const Launchers* launchers_4096f();
 
 const Launchers* launchers_for(int N, bool fp64) {
     switch (N) {
@@ -16,7 +15,7 @@ const Launchers* launchers_for(int N, bool fp64) {
     case 768:  return fp64 ? launchers_768d() : launchers_768f();
     case 1024: return fp64 ? launchers_1024d() : launchers_1024f();
     case 2048: return fp64 ? launchers_2048d() : launchers_2048f();
-    case 4096: return fp64 ? nullptr : launchers_4096f();
+    case 4096: return fp64 ? launchers_4096d() : launchers_4096f();
     default:   return nullptr;
     }
 }
@@ -30,7 +29,7 @@ bool shape_for(int N, bool fp64, ShapeInfo* out) {
     case 768:  s = fp64 ? shape_info<D768>() : shape_info<S768>(); break;
     case 1024: s = fp64 ? shape_info<D1024>() : shape_info<S1024>(); break;
     case 2048: s = fp64 ? shape_info<D2048>() : shape_info<S2048>(); break;
-    case 4096: if (fp64) return false; s = shape_info<S4096>(); break;
+    case 4096: s = fp64 ? shape_info<D4096>() : shape_info<S4096>(); break;
     default:   return false;
     }
     if (out) *out = s;

@@ -114,12 +114,13 @@ using D512  = Shape<512, 32, 4, 8, 8, 8>;
 using D768  = Shape<768, 32, 4, 8, 12, 8>;
 using D1024 = Shape<1024, 64, 2, 4, 16, 16>;
 using D2048 = Shape<2048, 64, 2, 8, 16, 16>;
+using D4096 = Shape<4096, 256, 2, 16, 16, 16>;
 
 static_assert(S256::valid() && S384::valid() && S512::valid() && S768::valid() &&
               S1024::valid() && S2048::valid() && S4096::valid(), "bad fp32 shape");
 static_assert(S512r::valid() && S1024r::valid() && S1024t::valid() && S2048r::valid(), "bad alternative shape");
 static_assert(D256::valid() && D384::valid() && D512::valid() && D768::valid() &&
-              D1024::valid() && D2048::valid(), "bad fp64 shape");
+              D1024::valid() && D2048::valid() && D4096::valid(), "bad fp64 shape");
 
 // Runtime description of a shape (host side).
 struct ShapeInfo {

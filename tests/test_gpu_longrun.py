@@ -118,6 +118,33 @@ def test_long_run_batched_sweep_vs_fp64():
         stats_agree(np.asarray(power[i]), p64, spec[i], s64)
 
 
+def test_long_run_structured_4096_batched_vs_fp64():
+    """16 x 4096^2 with the periodic pump: two of the cavities, 5000 round trips
+    batched in the FP32 form against each alone in the GPU FP64 form."""
+    trips, every = 5000, 100
+    cavs = structured_4096()[:2]
+    plans = [lsr.Plan(c) for c in cavs]
+    st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+    Es, Ns = [x[0] for x in st], [x[1] for x in st]
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    power = [[] for _ in cavs]
+    spec = [np.zeros(lsr.lsr_plan_nbins(p.handle)) for p in plans]
+    for k in range(trips // every):
+        lsr.lsr_batch_roundtrips(b, Es, Ns, every)
+        for i, (p, c) in enumerate(zip(plans, cavs)):
+            power[i].extend((1 - c.R) * p.trace(every)[:, 2] * c.dx ** 2)
+            if (k + 1) * every > trips // 2:
+                spec[i] += lsr.lsr_batch_diag(b, i, Es[i], Ns[i], spec[i].size)["radial"]
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.sync()
+        p.close()
+    del Es, Ns, st
+    for i, c in enumerate(cavs):
+        p64, s64 = long_run(c, lsr.LSR_PREC_FP64, trips, chunk=trips, spec_every=every)
+        stats_agree(np.asarray(power[i]), p64, spec[i], s64)
+
+
 def test_long_run_1024_fp32_vs_fp64():
     """1024^2, F=300, R=0.95, pump 3x, T1=2000, 10000 round trips."""
     cav = plain_1024()
