@@ -58,6 +58,7 @@ class _Params(ctypes.Structure):
         ("filter_delta", ctypes.c_double),
         ("model", ctypes.c_int),
         ("slices", ctypes.c_int),
+        ("rough", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -111,6 +112,7 @@ class CavityParams:
     filter_delta: float = 0.0   # > 0: Gaussian renormalization-group filter instead of Fresnel
     model: int = 0              # 0 B class (Euler), 1 B class (exact over a trip), 2 class A
     slices: int = 1             # thin gain sheets per iterate (inversion holds one N x N map each)
+    rough: np.ndarray | None = None  # N x N roughness phase psi (rad) of Eq. (12), or None
 
     def _c(self):
         p = _Params()
@@ -121,10 +123,13 @@ class CavityParams:
         p.filter_delta = self.filter_delta
         p.model = self.model
         p.slices = self.slices
-        keep = None
+        keep = []
         if self.ap_kind == 3:
-            keep = np.ascontiguousarray(self.ap_mask, dtype=np.float64).reshape(self.N, self.N)
-            p.ap_mask = _dp(keep)
+            keep.append(np.ascontiguousarray(self.ap_mask, dtype=np.float64).reshape(self.N, self.N))
+            p.ap_mask = _dp(keep[-1])
+        if self.rough is not None:
+            keep.append(np.ascontiguousarray(self.rough, dtype=np.float64).reshape(self.N, self.N))
+            p.rough = _dp(keep[-1])
         return p, keep
 
 

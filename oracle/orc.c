@@ -243,15 +243,15 @@ static int signed_index(int q, int n)
 }
 
 /* Complex aperture D of Eq. (12) at grid point (x, y): modulus D0 (finite
- * width of gain region / mirror) times the mirror-curvature phase
- * exp(i k r^2 / (2F)).  D0 is the super-Gaussian exp(-(r/r0)^m), the
- * Gaussian exp(-r^2/(2 r0^2)) of Eq. (26) (exponent read as 2 D_a^2, as in
- * Eq. (27)), 1, or a user mask. */
+ * width of gain region / mirror) times the phase exp(i k r^2 / (2F) + i psi)
+ * of a mirror of focal length F with surface roughness psi(x, y).  D0 is the
+ * super-Gaussian exp(-(r/r0)^m), the Gaussian exp(-r^2/(2 r0^2)) of Eq. (26)
+ * (exponent read as 2 D_a^2, as in Eq. (27)), 1, or a user mask. */
 static void aperture(const orc_params* p, int y, int x, double* ar, double* ai)
 {
     double xx = coord(x, p), yy = coord(y, p);
     double r2 = xx * xx + yy * yy;
-    double amp;
+    double amp, ph = 0.0;
     switch (p->ap_kind) {
     case 1: amp = exp(-pow(r2 / (p->ap_radius * p->ap_radius), 0.5 * p->ap_order)); break;
     case 2: amp = exp(-r2 / (2.0 * p->ap_radius * p->ap_radius)); break;
@@ -260,13 +260,11 @@ static void aperture(const orc_params* p, int y, int x, double* ar, double* ai)
     }
     if (p->focal != 0.0 && isfinite(p->focal)) {
         double k = 2.0 * M_PI / p->lambda;
-        double ph = k * r2 / (2.0 * p->focal);
-        *ar = amp * cos(ph);
-        *ai = amp * sin(ph);
-    } else {
-        *ar = amp;
-        *ai = 0.0;
+        ph = k * r2 / (2.0 * p->focal);
     }
+    if (p->rough) ph += p->rough[(size_t)y * p->N + x];
+    *ar = amp * cos(ph);
+    *ai = amp * sin(ph);
 }
 
 /* Pump N0(r): uniform, or the spatially periodic gain N0(r) = N0(r + p) of

@@ -49,6 +49,9 @@ typedef struct {
                            holding its own inversion (the distributed-gain
                            variant noted in Sec. 2.2 after Eq. (12)); see
                            orc_run                                          */
+    const double* rough;/* N*N phase psi (rad) of the mirror roughness, the
+                           random term of the complex aperture of Eq. (12);
+                           row-major; NULL = smooth mirror                  */
 } orc_params;
 
 /* One-dimensional DFT of length n = 2^a 3^b, in place, unnormalized.

@@ -18,7 +18,12 @@ Recipe (used for every workload; the paper's cavity numbers are context only):
   PCG64 generator seeded with 14102855 + cavity index; the oracle receives it
   as complex128, the GPU the same array rounded to complex64;
 * initial inversion N = N0 everywhere; with m thin gain sheets, N0/m on every
-  sheet (the inversion array is then m x N x N, sheet 0 at the mirror).
+  sheet (the inversion array is then m x N x N, sheet 0 at the mirror);
+* mirror roughness (off unless asked for): a phase field psi(x, y) drawn as
+  white Gaussian noise (PCG64 seeded with 14102855 + 500009 + cavity index),
+  smoothed by a circular moving average `rough_corr` cells wide along each
+  axis and scaled to the rms `rough_rms` (rad).  Both sides receive the same
+  float64 array.
 """
 from __future__ import annotations
 
@@ -30,6 +35,7 @@ import numpy as np
 LAMBDA = 1.064e-6     # m
 L_CAV = 2.0e-3        # m
 SEED_BASE = 14102855
+ROUGH_SEED_OFFSET = 500009
 NOISE_SIGMA = 1.0e-3
 
 
@@ -55,6 +61,8 @@ class Cavity:
     filter_delta: float = 0.0  # > 0: real renormalization-group filter (m) instead of Fresnel
     model: int = 0             # 0 B class (Euler update), 1 B class (exact update), 2 class A
     slices: int = 1            # thin gain sheets per round trip
+    rough_rms: float = 0.0     # rms of the mirror roughness phase (rad); 0 = smooth mirror
+    rough_corr: int = 4        # its correlation width (grid cells)
 
     @property
     def a(self) -> float:
@@ -91,6 +99,29 @@ def noise_field(N: int, index: int, sigma: float = NOISE_SIGMA) -> np.ndarray:
     return (re * s + 1j * (im * s)).astype(np.complex128)
 
 
+def roughness_phase(N: int, index: int, rms: float, corr: int = 4) -> np.ndarray:
+    """Seeded smooth random phase field psi (rad), float64 (N, N), of rms `rms`:
+    white Gaussian noise averaged over a circular window `corr` cells wide
+    along each axis, then scaled."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + ROUGH_SEED_OFFSET + index))
+    w = rng.standard_normal((N, N))
+    k = max(1, int(corr))
+    for axis in (0, 1):
+        acc = np.zeros_like(w)
+        for s in range(k):
+            acc += np.roll(w, s, axis=axis)
+        w = acc
+    w -= w.mean()
+    return w * (rms / math.sqrt(np.mean(w * w)))
+
+
+def rough_field(cav: "Cavity") -> np.ndarray | None:
+    """The cavity's roughness phase, or None for a smooth mirror."""
+    if not cav.rough_rms:
+        return None
+    return roughness_phase(cav.N, cav.index, cav.rough_rms, cav.rough_corr)
+
+
 def initial_state(cav: Cavity):
     """(E0 complex128, Ninv0 float64) for a cavity; Ninv0 is (m, N, N) with
     m > 1 gain sheets."""
@@ -109,7 +140,8 @@ def oracle_params(cav: Cavity):
                         N0=cav.N0, T1=cav.T1, focal=cav.focal, ap_kind=cav.ap_kind,
                         ap_radius=cav.ap_radius, ap_order=cav.ap_order,
                         mod_amp=cav.mod_amp, mod_period=cav.mod_period,
-                        filter_delta=cav.filter_delta, model=cav.model, slices=cav.slices)
+                        filter_delta=cav.filter_delta, model=cav.model, slices=cav.slices,
+                        rough=rough_field(cav))
 
 
 # --------------------------------------------------------------------------
