@@ -116,7 +116,7 @@ typedef struct {
  * uploaded once; no allocation happens in later calls except lsr_diag's
  * first use of its spectrum scratch and table replacement by
  * lsr_plan_set_gain / lsr_plan_set_filter / lsr_plan_set_slices /
- * lsr_propagate. */
+ * lsr_plan_set_roughness / lsr_propagate. */
 int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L,
                     double F, double R, const lsr_aperture* ap, lsr_prec prec);
 
@@ -182,6 +182,19 @@ int lsr_plan_set_filter(lsr_plan p, double delta);
  * LSR_EINVAL unless 1 <= m <= LSR_MAX_SLICES. */
 #define LSR_MAX_SLICES 64
 int lsr_plan_set_slices(lsr_plan p, int m);
+
+/* Mirror roughness: the random phase psi(x, y) of the complex aperture of
+ * Sec. 2.2, Eq. (12), D = D0 exp(i k r^2/(2F) + i psi), on top of the
+ * curvature phase of F.  psi: HOST array of N*N doubles (rad), row-major
+ * (element (row y, column x) at y*N + x), read during the call only; NULL
+ * restores the smooth mirror.  The plan builds exp(i psi) in FP64 (each angle
+ * reduced to one turn first), keeps it in device memory in its precision
+ * (8 B per point, 16 for FP64 plans) and applies it in the local step at the
+ * mirror sheet: the row pass then reads that many more bytes per point.
+ * Waits for the plan's stream and allocates the table (the previous one is
+ * freed); batches holding the plan pick the change up on their next call.
+ * Diagnostics (lsr_diag) include it.  LSR_EINVAL for a non-finite psi. */
+int lsr_plan_set_roughness(lsr_plan p, const double* psi);
 
 /* Pump and relaxation (Eq. (1), second line; periodic pump of Sec. 3):
  * N0(x,y) = N0 (1 + mod_amp cos(2 pi x/mod_period) cos(2 pi y/mod_period)),

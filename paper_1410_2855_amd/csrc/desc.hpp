@@ -33,6 +33,7 @@ struct CavDesc {
     const void* pump_c;     // cos(2 pi x_i / d), N entries, or null (uniform pump)
     const void* foc;        // exp(i pi x_i^2/(lambda F)), N complex entries, or null (flat mirror)
     const void* mask;       // N*N aperture amplitude (AP_MASK) or null
+    const void* rough;      // N*N exp(i psi) of the mirror roughness psi, complex, or null
     void* scratch;          // DIAG: tiled forward row transform of G (N*N complex)
     double* partials;       // per row block: 4 sums
     double* radial_part;    // DIAG: per column block radial spectrum partials

@@ -68,6 +68,7 @@ struct lsr_plan_s {
     void* d_foc = nullptr;
     void* d_hz = nullptr;            // propagator table of the last lsr_propagate distance
     void* d_hs = nullptr;            // nonlocal step between two of several gain sheets
+    void* d_rough = nullptr;         // exp(i psi) of the mirror roughness, N*N complex, or null
     double* d_partials = nullptr;
     double* d_trace = nullptr;
     unsigned* d_counters = nullptr;

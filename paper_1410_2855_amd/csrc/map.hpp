@@ -266,6 +266,8 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
     const int kind = d.ap_kind;
     const T* pc = static_cast<const T*>(d.pump_c);
     const cx<T>* foc = static_cast<const cx<T>*>(d.foc);
+    const void* rough = d.rough;
+    const bool phased = foc || rough;
     // byte offsets of row y from the cavity's (uniform) array bases
     const unsigned row = (unsigned)y * (unsigned)S::N * (unsigned)sizeof(T);
 
@@ -317,7 +319,15 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
             acc[2] = fma_(aeh * aeh, I, acc[2]);
             acc[3] += n;
             cx<T> g = scale(e, sqR * aeh);
-            if (foc) g = cmul(g, cmul(gld<cx<T>>(foc, (unsigned)sizeof(cx<T>) * x), fy));
+            // phase of the complex aperture: mirror curvature exp(i k r^2/(2F))
+            // as the product of its x and y factors, then the roughness
+            // exp(i psi(x, y)).  One branch per point, as many as a smooth
+            // flat mirror needs; hoisting these loads out of the point loop
+            // costs registers.
+            if (phased) {
+                if (foc) g = cmul(g, cmul(gld<cx<T>>(foc, (unsigned)sizeof(cx<T>) * x), fy));
+                if (rough) g = cmul(g, gld<cx<T>>(rough, 2u * row + (unsigned)sizeof(cx<T>) * x));
+            }
             v[i] = g;
             if constexpr (MODE != ROW_DIAG) {
                 const T pump = pc ? N0 * fma_(mamp * gld<T>(pc, (unsigned)sizeof(T) * x), pcy, (T)1) : N0;

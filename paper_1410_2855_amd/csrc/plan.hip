@@ -152,7 +152,7 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 static void free_plan_memory(lsr_plan_s* p) {
     void* bufs[] = {p->d_tw, p->d_hx, p->d_pump, p->d_foc, p->d_partials, p->d_trace,
                     p->d_counters, p->d_scratch, p->d_radial_part, p->d_diag_out, p->d_hz,
-                    p->d_hs};
+                    p->d_hs, p->d_rough};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -222,6 +222,7 @@ static CavDesc sheet_desc(const lsr_plan_s* p, void* E, void* Ninv, int k) {
         d.ap_kind = AP_NONE;
         d.mask = nullptr;
         d.foc = nullptr;
+        d.rough = nullptr;
     }
     return d;
 }
@@ -357,6 +358,7 @@ int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L, do
     d.pump_c = nullptr;
     d.foc = p->d_foc;
     d.mask = a.kind == 3 ? a.mask : nullptr;
+    d.rough = nullptr;
     d.partials = p->d_partials;
     d.trace = p->d_trace;
     d.counters = p->d_counters;
@@ -451,6 +453,37 @@ int lsr_plan_set_filter(lsr_plan p, double delta) {
     p->filter = delta;
     p->d.hx = t;
     p->d.prop_kind = delta > 0 ? 1 : 0;
+    ++p->version;
+    return LSR_OK;
+}
+
+int lsr_plan_set_roughness(lsr_plan p, const double* psi) {
+    if (!p) return set_err(LSR_EINVAL, "plan is NULL");
+    const size_t nn = (size_t)p->N * (size_t)p->N;
+    void* t = nullptr;
+    if (psi) {
+        // exp(i psi) in FP64, each angle reduced to one turn first
+        std::vector<double> tab(2 * nn);
+        for (size_t i = 0; i < nn; ++i) {
+            if (!std::isfinite(psi[i])) return set_err(LSR_EINVAL, "roughness phase %zu is not finite", i);
+            const double turns = psi[i] / kTwoPi;
+            const double f = turns - floor(turns);
+            tab[2 * i] = cos(kTwoPi * f);
+            tab[2 * i + 1] = sin(kTwoPi * f);
+        }
+        DeviceGuard g(p->device);
+        int rc = upload(&t, tab, p->prec != PREC_FP64);
+        if (rc) return rc;
+    }
+    DeviceGuard g(p->device);
+    if (hipStreamSynchronize(p->stream) != hipSuccess) {
+        if (t) (void)hipFree(t);
+        return set_err(LSR_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    // the old table is no longer read by enqueued work
+    if (p->d_rough) (void)hipFree(p->d_rough);
+    p->d_rough = t;
+    p->d.rough = t;
     ++p->version;
     return LSR_OK;
 }

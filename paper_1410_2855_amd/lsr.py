@@ -56,6 +56,7 @@ _SIGS = {
     "lsr_plan_set_filter": (_i, [_vp, _d]),
     "lsr_plan_set_model": (_i, [_vp, _i]),
     "lsr_plan_set_slices": (_i, [_vp, _i]),
+    "lsr_plan_set_roughness": (_i, [_vp, _vp]),
     "lsr_propagate": (_i, [_vp, _vp, _d, _vp]),
     "lsr_plan_set_stream": (_i, [_vp, _vp]),
     "lsr_roundtrips": (_i, [_vp, _vp, _vp, _i]),
@@ -190,6 +191,15 @@ def lsr_plan_set_slices(plan, m: int):
     _check(load().lsr_plan_set_slices(plan, int(m)))
 
 
+def lsr_plan_set_roughness(plan, psi):
+    """psi: host N x N float64 roughness phase (rad), or None for a smooth mirror."""
+    if psi is None:
+        _check(load().lsr_plan_set_roughness(plan, None))
+        return
+    a = np.ascontiguousarray(psi, dtype=np.float64)
+    _check(load().lsr_plan_set_roughness(plan, a.ctypes.data))
+
+
 def lsr_propagate(plan, E_in, z: float, E_out):
     _check(load().lsr_propagate(plan, _ptr(E_in), float(z), _ptr(E_out)))
 
@@ -314,6 +324,9 @@ class Plan:
             lsr_plan_set_model(self.handle, cav.model)
         if getattr(cav, "slices", 1) != 1:
             lsr_plan_set_slices(self.handle, cav.slices)
+        if getattr(cav, "rough_rms", 0.0):
+            from .inputs import rough_field
+            lsr_plan_set_roughness(self.handle, rough_field(cav))
         lsr_plan_set_stream(self.handle, stream if stream is not None else torch.cuda.current_stream())
 
     @property

@@ -142,6 +142,9 @@ def test_argument_validation_without_a_device():
     with pytest.raises(lsr.LsrError) as ei:
         lsr.lsr_roundtrips(None, None, None, 1)
     assert ei.value.code == lsr.LSR_EINVAL
+    with pytest.raises(lsr.LsrError) as ei:
+        lsr.lsr_plan_set_roughness(None, np.zeros((4, 4)))
+    assert ei.value.code == lsr.LSR_EINVAL
 
 
 @pytest.mark.parametrize("sizes,lag", [([1024] * 5, -1), ([256, 384, 512, 768, 1024] * 3, 0),

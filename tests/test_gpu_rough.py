@@ -1,0 +1,205 @@
+"""Mirror roughness: the random phase psi of the complex aperture of Sec. 2.2,
+Eq. (12), D = D0 exp(i k r^2/(2F) + i psi), on the GPU against the FP64
+oracle, in the batched path against the one-cavity path, and against the
+beam walk-off that a linear psi fixes."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1410_2855_amd.inputs import Cavity, initial_state, oracle_params, rough_field, sweep
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1410_2855_amd import lsr  # noqa: E402
+
+TAB, PLAIN, F64 = lsr.LSR_PREC_FP64TAB, lsr.LSR_PREC_PLAIN, lsr.LSR_PREC_FP64
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def rough(N=512, **kw):
+    d = dict(N=N, F=180.0, R=0.88, pump_ratio=3.0, T1=300.0, index=61, rough_rms=0.8, rough_corr=4)
+    d.update(kw)
+    return Cavity(**d)
+
+
+def run_both(cav, prec, trips):
+    e0, n0 = initial_state(cav)
+    p = lsr.Plan(cav, prec=prec)
+    e, n = p.state(e0, n0)
+    p.roundtrips(e, n, trips)
+    p.sync()
+    tr = p.trace(trips)
+    p.close()
+    eo, no, to = oracle.run(oracle_params(cav), e0, n0, trips)
+    return (e.cpu().numpy(), n.cpu().numpy(), tr), (eo, no, to)
+
+
+@pytest.mark.parametrize("focal", [math.inf, 4.0])
+@pytest.mark.parametrize("prec,trips,tol", [(TAB, 50, 1e-5), (PLAIN, 10, 1e-3), (F64, 150, 1e-11)])
+def test_roughness_matches_oracle(focal, prec, trips, tol):
+    cav = rough(focal=focal * 2e-3)
+    (eg, ng, tg), (eo, no, to) = run_both(cav, prec, trips)
+    assert rel(eg, eo) <= tol and rel(ng, no) <= tol
+    assert rel(tg, to) <= max(tol, cav.N ** 2 * 2.3e-16)
+
+
+@pytest.mark.parametrize("N", [256, 384, 768, 1024, 2048, 4096])
+def test_roughness_every_size(N):
+    cav = rough(N=N, F=1000.0 if N >= 2048 else 300.0, rough_rms=1.5, rough_corr=2)
+    trips = 1 if N == 4096 else 4
+    (eg, ng, _), (eo, no, _) = run_both(cav, TAB, trips)
+    assert rel(eg, eo) <= 2e-6 and rel(ng, no) <= 2e-6, N
+
+
+@pytest.mark.parametrize("variant", ["sheets", "filter", "class-a", "pump-mod", "mask"])
+def test_roughness_with_the_other_forms(variant):
+    """With 3 gain sheets psi acts at the mirror sheet only."""
+    cav = rough()
+    if variant == "mask":
+        m = np.random.default_rng(8).uniform(0.5, 1.0, (cav.N, cav.N))
+        e0, n0 = initial_state(cav)
+        mask = torch.tensor(m, dtype=torch.float32, device="cuda")
+        p = lsr.Plan(cav.with_(rough_rms=0.0))
+        lsr.lsr_plan_destroy(p.handle)
+        p.handle = lsr.lsr_plan_create(cav.N, cav.dx, cav.lam, cav.L, 0.0, cav.R, ap_kind=lsr.LSR_AP_MASK,
+                                       ap_mask=mask)
+        lsr.lsr_plan_set_gain(p.handle, cav.N0, cav.T1)
+        lsr.lsr_plan_set_roughness(p.handle, rough_field(cav))
+        lsr.lsr_plan_set_stream(p.handle, torch.cuda.current_stream())
+        e, n = p.state(e0, n0)
+        p.roundtrips(e, n, 30)
+        p.sync()
+        params = oracle_params(cav)
+        params.ap_kind, params.ap_mask = 3, m.astype(np.float32).astype(np.float64)
+        eo, no, _ = oracle.run(params, e0, n0, 30)
+        assert rel(e.cpu().numpy(), eo) <= 1e-5 and rel(n.cpu().numpy(), no) <= 1e-5
+        p.close()
+        return
+    cav = {"sheets": cav.with_(slices=3), "filter": cav.with_(filter_delta=2.5 * cav.dx),
+           "class-a": cav.with_(model=2), "pump-mod": cav.with_(mod_amp=0.3, mod_periods=16)}[variant]
+    trips = 16 if variant == "sheets" else 50
+    (eg, ng, _), (eo, no, _) = run_both(cav, TAB, trips)
+    assert rel(eg, eo) <= 1e-5 and rel(ng, no) <= 1e-5
+
+
+def test_cleared_roughness_is_the_smooth_mirror_bitwise_and_bad_phases_fail():
+    cav = rough(N=256)
+    e0, n0 = initial_state(cav)
+    out = []
+    for toggle in (False, True):
+        p = lsr.Plan(cav.with_(rough_rms=0.0))
+        if toggle:
+            lsr.lsr_plan_set_roughness(p.handle, rough_field(cav))
+            lsr.lsr_plan_set_roughness(p.handle, None)
+        e, n = p.state(e0, n0)
+        p.roundtrips(e, n, 7)
+        p.sync()
+        out.append((e.cpu(), n.cpu(), p.trace(7)))
+        if toggle:
+            bad = rough_field(cav)
+            bad[3, 5] = np.nan
+            with pytest.raises(lsr.LsrError) as ei:
+                lsr.lsr_plan_set_roughness(p.handle, bad)
+            assert ei.value.code == lsr.LSR_EINVAL
+        p.close()
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
+
+
+def test_linear_roughness_walks_the_beam_off_on_the_gpu():
+    """psi = 2 pi x / (N dx) tilts the beam; after one trip of a passive cavity
+    (R = 1, no gain, no aperture) it has moved N / (4 F_fresnel) = 4 cells in
+    +x and kept its shape (FP64 form, against the shifted smooth-mirror trip
+    of the same path)."""
+    N, Ff = 256, 16.0
+    cav = Cavity(N=N, F=Ff, R=1.0, pump_ratio=0.0, T1=1.0, ap_kind=0, index=0)
+    x = (np.arange(N) - N / 2) * cav.dx
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    e0 = np.exp(-((X - 5 * cav.dx) ** 2 + Y ** 2) / (9 * cav.dx) ** 2).astype(np.complex128)
+    n0 = np.zeros((N, N))
+    psi = 2 * math.pi * X / (N * cav.dx)
+    out = []
+    for ph in (None, psi):
+        p = lsr.Plan(cav, prec=F64)
+        lsr.lsr_plan_set_roughness(p.handle, ph)
+        e, n = p.state(e0, n0)
+        p.roundtrips(e, n, 1)
+        p.sync()
+        out.append(e.cpu().numpy())
+        p.close()
+    flat, tilt = out
+    s = round(N / (4 * Ff))
+    want = np.exp(1j * psi) * np.roll(flat, s, axis=1)
+    big = np.abs(want) > 1e-3 * np.max(np.abs(want))
+    ratio = tilt[big] / want[big]
+    assert np.max(np.abs(ratio - ratio[0])) <= 1e-10 and abs(abs(ratio[0]) - 1) <= 1e-10
+
+
+def test_diag_includes_the_roughness():
+    cav = rough(N=512, rough_rms=2.0, rough_corr=1)
+    e0, n0 = initial_state(cav)
+    p = lsr.Plan(cav)
+    e, n = p.state(e0, n0)
+    d = p.diag(e, n)
+    p.close()
+    radial, dom = oracle.spectrum(oracle_params(cav), e0, n0)
+    smooth, _ = oracle.spectrum(oracle_params(cav.with_(rough_rms=0.0)), e0, n0)
+    assert rel(d["radial"], radial) <= 1e-5
+    assert rel(smooth, radial) >= 1e-2        # the phase screen does change the spectrum
+    assert d["dominant_bin"] == dom
+
+
+@pytest.mark.parametrize("engine", [0, 1, 2])
+def test_rough_cavities_in_a_batch_are_the_plain_path_bitwise(engine):
+    cavs = [c.with_(rough_rms=0.6 if i % 2 else 0.0) for i, c in enumerate(sweep(6, seed=5, sizes=(256, 512, 1024)))]
+    trips = 9
+
+    def fresh():
+        plans = [lsr.Plan(c) for c in cavs]
+        st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+        return plans, [s[0] for s in st], [s[1] for s in st]
+
+    plans, Es, Ns = fresh()
+    for p, e, n in zip(plans, Es, Ns):
+        p.roundtrips(e, n, trips)
+        p.sync()
+    ref = [(e.clone(), n.clone(), p.trace(trips)) for p, e, n in zip(plans, Es, Ns)]
+    for p in plans:
+        p.close()
+    plans, Es, Ns = fresh()
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_configure(b, engine=engine, shape=0)
+    lsr.lsr_batch_set_graph_trips(b, 4)
+    lsr.lsr_batch_roundtrips(b, Es, Ns, trips)
+    for p in plans:
+        p.sync()
+    for i, (p, e, n) in enumerate(zip(plans, Es, Ns)):
+        assert torch.equal(e, ref[i][0]) and torch.equal(n, ref[i][1]), i
+        assert np.array_equal(p.trace(trips), ref[i][2]), i
+    # the roughness switched on for cavity 0 between calls reaches the batch
+    lsr.lsr_plan_set_roughness(plans[0].handle, rough_field(cavs[0].with_(rough_rms=0.9)))
+    e0, n0 = initial_state(cavs[0])
+    solo = lsr.Plan(cavs[0].with_(rough_rms=0.9))
+    es, ns = solo.state(e0, n0)
+    ea, na = plans[0].state(e0, n0)
+    Es[0].copy_(ea)
+    Ns[0].copy_(na)
+    lsr.lsr_batch_roundtrips(b, Es, Ns, 3)
+    solo.roundtrips(es, ns, 3)
+    for p in plans:
+        p.sync()
+    solo.sync()
+    assert torch.equal(Es[0], es) and torch.equal(Ns[0], ns)
+    solo.close()
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
