@@ -1,6 +1,7 @@
 """Randomised combinations of the map's options on the GPU against the FP64
 oracle: grid size, Fresnel number, mirror reflectivity and curvature,
-aperture form, pump level and modulation, relaxation time, local-step model,
+aperture form, mirror roughness, pump level and modulation, relaxation
+time, local-step model,
 nonlocal step (Fresnel or filter), number of gain sheets and precision form,
 drawn from one seeded generator.  Each case runs a few round trips and must
 match the oracle to the single-cavity bar."""
@@ -42,6 +43,8 @@ def draw(i):
     cav = cav.with_(model=int(r.choice([0, 0, 1, 2])), slices=int(r.choice([1, 1, 2, 3])))
     prec = int(r.choice([lsr.LSR_PREC_FP64TAB, lsr.LSR_PREC_FP64TAB, lsr.LSR_PREC_FP64]))
     trips = int(r.integers(3, 8))
+    if r.random() < 0.3:   # drawn last, so the other options of a case stay as they were
+        cav = cav.with_(rough_rms=float(r.uniform(0.2, 2.0)), rough_corr=int(r.integers(1, 6)))
     return cav, prec, trips
 
 
@@ -59,8 +62,8 @@ def test_random_cavity_matches_oracle(i):
     p.close()
     eo, no, to = oracle.run(oracle_params(cav), e0, n0, trips)
     tol = 1e-11 if prec == lsr.LSR_PREC_FP64 else 5e-6
-    case = "N=%d F=%.0f model=%d sheets=%d filter=%s prec=%d trips=%d" % (
-        cav.N, cav.F, cav.model, cav.slices, cav.filter_delta > 0, prec, trips)
+    case = "N=%d F=%.0f model=%d sheets=%d filter=%s rough=%.2f prec=%d trips=%d" % (
+        cav.N, cav.F, cav.model, cav.slices, cav.filter_delta > 0, cav.rough_rms, prec, trips)
     assert rel(e.cpu().numpy(), eo) <= tol, case
     assert rel(n.cpu().numpy(), no) <= tol, case
     assert rel(tr, to) <= max(tol, cav.N ** 2 * 2.3e-16), case
