@@ -29,6 +29,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 ROW_BYTES_PER_PT = 24          # row pass: field read+write 16 B, inversion read+write 8 B
 COL_BYTES_PER_PT = 16          # column pass: field read+write 16 B
 TRIP_BYTES_PER_PT = ROW_BYTES_PER_PT + COL_BYTES_PER_PT
+ROUGH_BYTES_PER_PT = 8         # row pass with mirror roughness: exp(i psi) read, complex64
 TUNE_CACHE = os.path.join(ROOT, "paper_1410_2855_amd", "tune_cache.json")
 
 
@@ -271,6 +272,9 @@ def main():
     ap.add_argument("--filter-delta", type=float, default=0.0,
                     help="> 0: the renormalization-group filter of this width, in grid spacings, "
                          "replaces the Fresnel step")
+    ap.add_argument("--rough-rms", type=float, default=0.0,
+                    help="> 0: every cavity's mirror carries a random roughness phase of this rms (rad), "
+                         "4-cell correlation; the row pass then also reads exp(i psi), 8 B per point")
     ap.add_argument("--autotune", action="store_true", help="retune the batch and update the cache")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
@@ -316,6 +320,13 @@ def main():
         cavs = [c.with_(model=model, filter_delta=args.filter_delta * c.dx) for c in cavs]
         workload += "; local step %s%s" % (args.local_step, ", filter %.3g dx" % args.filter_delta
                                            if args.filter_delta > 0 else "")
+    # the counter summaries cover the default map only
+    variant = bool(model or args.filter_delta > 0 or args.rough_rms > 0)
+    row_bpp = ROW_BYTES_PER_PT
+    if args.rough_rms > 0:
+        cavs = [c.with_(rough_rms=args.rough_rms) for c in cavs]
+        workload += "; mirror roughness %.3g rad rms" % args.rough_rms
+        row_bpp += ROUGH_BYTES_PER_PT
     plans, Es, Ns = [], [], []
     for c in cavs:
         p = lsr.Plan(c, prec=lsr.LSR_PREC_FP64TAB, stream=stream)
@@ -367,14 +378,14 @@ def main():
     if cfg["engine"] >= 1:
         # grouped launches (engine 1, or its software-pipelined form 2): one
         # kernel per pass
-        kernels = {"row_pass": (row_ms, ROW_BYTES_PER_PT * pts), "column_pass": (col_ms, COL_BYTES_PER_PT * pts)}
+        kernels = {"row_pass": (row_ms, row_bpp * pts), "column_pass": (col_ms, COL_BYTES_PER_PT * pts)}
     else:
-        kernels = {"round_trip": (row_ms, TRIP_BYTES_PER_PT * pts)}
+        kernels = {"round_trip": (row_ms, (row_bpp + COL_BYTES_PER_PT) * pts)}
     dom = max(kernels, key=lambda k: kernels[k][0])
     ms, nbytes = kernels[dom]
     achieved = nbytes / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, pts),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None if variant else load_traffic(dom, pts),
                 "kernel": dom, "launch_ms": round(ms, 5), "algorithmic_bytes_per_launch": nbytes,
                 "bytes_per_point": nbytes // pts,
                 "other_kernels_ms": {k: round(v[0], 5) for k, v in kernels.items() if k != dom},
@@ -399,7 +410,7 @@ def main():
                    "engine": ENGINES.get(cfg["engine"], "?"), "launch": cfg},
         "plain": {"value": plain_value, "ms_per_step": t_plain * 1e3},
         "speedup_batched_vs_plain": value / plain_value,
-        "hbm_frac_whole_step": round(pts * TRIP_BYTES_PER_PT / t_step / 1e9 / HBM_PEAK_GBS, 4),
+        "hbm_frac_whole_step": round(pts * (row_bpp + COL_BYTES_PER_PT) / t_step / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
     }
 

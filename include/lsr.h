@@ -191,9 +191,11 @@ int lsr_plan_set_slices(lsr_plan p, int m);
  * reduced to one turn first), keeps it in device memory in its precision
  * (8 B per point, 16 for FP64 plans) and applies it in the local step at the
  * mirror sheet: the row pass then reads that many more bytes per point.
- * Waits for the plan's stream and allocates the table (the previous one is
- * freed); batches holding the plan pick the change up on their next call.
- * Diagnostics (lsr_diag) include it.  LSR_EINVAL for a non-finite psi. */
+ * Rough plans run on kernels compiled with the roughness factor (the default
+ * kernels carry none); a batch holding the plan regroups on its next call,
+ * as after a model change.  Waits for the plan's stream and allocates the
+ * table (the previous one is freed).  Diagnostics (lsr_diag) include it.
+ * LSR_EINVAL for a non-finite psi. */
 int lsr_plan_set_roughness(lsr_plan p, const double* psi);
 
 /* Pump and relaxation (Eq. (1), second line; periodic pump of Sec. 3):

@@ -198,7 +198,7 @@ struct lsr_batch_s {
     std::vector<BatchGroup> grp;
     std::vector<void*> lastE, lastN;
     std::vector<unsigned> lastVer;   // plan descriptor versions of the last upload
-    std::vector<int> models;         // the plans' local-step models when grouped
+    std::vector<int> models;         // the plans' local-step codes (model, roughness) when grouped
     Tune tune;
     std::string key;
     hipGraphExec_t graph = nullptr;
@@ -280,13 +280,14 @@ static int batch_pack(lsr_batch_s* b) {
 // alternative plan) and packs their task lists.
 static int batch_partition(lsr_batch_s* b) {
     groups_free(b);
-    // sizes with a cavity of another local-step model than the default run
-    // on kernels that read each cavity's model (key -N, one group per size)
+    // sizes with a cavity of another local-step code than the default (another
+    // model, or a rough mirror) run on kernels that read each cavity's code
+    // (key -N, one group per size)
     b->models.clear();
     std::map<int, bool> other_model;
     for (auto* q : b->plans) {
-        b->models.push_back(q->model);
-        other_model[q->N] = other_model[q->N] || q->model != 0;
+        b->models.push_back(q->d.model);
+        other_model[q->N] = other_model[q->N] || q->d.model != 0;
     }
     std::map<int, std::vector<int>> parts;
     for (int i = 0; i < (int)b->plans.size(); ++i) {
@@ -447,6 +448,9 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
         std::vector<CavDesc> h;
         for (int c : g.cav) {
             CavDesc d = b->plans[c]->d;
+            // the roughness kernels read d.rough without a check
+            if (((d.model & MODEL_ROUGH) != 0) != (d.rough != nullptr))
+                return set_err(LSR_EINVAL, "cavity %d: roughness code and table disagree", c);
             d.E = E[c];
             d.Ninv = N[c];
             if (g.d_tw) d.tw = g.d_tw;
@@ -463,11 +467,11 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
     return LSR_OK;
 }
 
-// A plan's local-step model changed since the batch was grouped: regroup
-// (the kernels of a group read the models it was built for).
+// A plan's local-step code (model, roughness) changed since the batch was
+// grouped: regroup (the kernels of a group read the codes it was built for).
 static int regroup_if_models_changed(lsr_batch_s* b) {
     bool same = b->models.size() == b->plans.size();
-    for (size_t i = 0; same && i < b->plans.size(); ++i) same = b->models[i] == b->plans[i]->model;
+    for (size_t i = 0; same && i < b->plans.size(); ++i) same = b->models[i] == b->plans[i]->d.model;
     if (same) return LSR_OK;
     LSR_HIP(hipStreamSynchronize(b->stream));
     drop_graph(b);

@@ -24,6 +24,10 @@ enum ColMode : int { COL_PROP = 0, COL_DIAG = 1, COL_FREE = 2 };
 //  [2] set when a batched column task gave up waiting for its row pass
 enum : int { CNT_TRIPS = 0, CNT_NONFINITE = 1, CNT_HANG = 2, CNT_WORDS = 16 };
 
+// Bit of the local-step code selecting the kernels that apply the mirror
+// roughness table (the others carry no code for it).
+enum : int { MODEL_ROUGH = 4, MODEL_MASK = 3 };
+
 struct CavDesc {
     void* E;                // field (row-major between calls, tiled inside)
     void* Ninv;             // inversion, row-major
@@ -47,8 +51,10 @@ struct CavDesc {
     int nrb;                // row blocks = column blocks = N / LPW
     int nbins;
     int prop_kind;          // 0 Fresnel propagator (hx), 1 real filter table (hx holds it)
-    int model;              // local step: 0 B class (Euler update), 1 B class (exact
-                            // update over a trip), 2 class A (saturable gain)
+    int model;              // local-step code: bits 0-1 the model, 0 B class (Euler
+                            // update), 1 B class (exact update over a trip), 2 class A
+                            // (saturable gain); MODEL_ROUGH set exactly when rough is
+                            // non-null
     double sqrtR;
     double N0, inv_T1, mod_amp;
     double dx;

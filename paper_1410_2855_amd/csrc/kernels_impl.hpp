@@ -41,10 +41,15 @@ int launch_row_m(const CavDesc& d, int mode, hipStream_t st) {
 
 template <class S, typename T>
 int launch_row_t(const CavDesc& d, int mode, hipStream_t st) {
+    // the roughness kernels read d.rough without a check
+    if (((d.model & MODEL_ROUGH) != 0) != (d.rough != nullptr)) return -1;
     switch (d.model) {
     case 0: return launch_row_m<S, T, 0>(d, mode, st);
     case 1: return launch_row_m<S, T, 1>(d, mode, st);
     case 2: return launch_row_m<S, T, 2>(d, mode, st);
+    case MODEL_ROUGH + 0: return launch_row_m<S, T, MODEL_ROUGH + 0>(d, mode, st);
+    case MODEL_ROUGH + 1: return launch_row_m<S, T, MODEL_ROUGH + 1>(d, mode, st);
+    case MODEL_ROUGH + 2: return launch_row_m<S, T, MODEL_ROUGH + 2>(d, mode, st);
     default: return -1;
     }
 }

@@ -248,8 +248,9 @@ __device__ __forceinline__ void finalize_sums(const CavDesc& d) {
 // Local step, inversion update and diagnostics sums on the lane's points of
 // row y (register order of the first forward radix = natural x order).  Done
 // in phases over all P points so the aperture power runs as one uniform loop.
-// MODEL selects the local step (0 B class with the Euler update, 1 B class
-// with the update exact over a trip, 2 class A); a compile-time choice, so the
+// MODEL is the local-step code: its low bits select the local step (0 B class
+// with the Euler update, 1 B class with the update exact over a trip, 2 class
+// A), MODEL_ROUGH adds the roughness factor.  A compile-time choice, so the
 // default kernels carry no code or registers of the others.
 template <class S, typename T, int MODE, int MODEL = 0>
 __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc& d, int y, int lane,
@@ -257,6 +258,8 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
     constexpr int R = R_FIRST<S>;
     constexpr int B = S::P / R;
     constexpr int P = S::P;
+    constexpr int LS = MODEL & MODEL_MASK;
+    constexpr bool ROUGH = (MODEL & MODEL_ROUGH) != 0;
     const T dx = (T)d.dx;
     const T half = (T)(0.5 * S::N);
     const T Y = ((T)y - half) * dx;
@@ -267,7 +270,6 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
     const T* pc = static_cast<const T*>(d.pump_c);
     const cx<T>* foc = static_cast<const cx<T>*>(d.foc);
     const void* rough = d.rough;
-    const bool phased = foc || rough;
     // byte offsets of row y from the cavity's (uniform) array bases
     const unsigned row = (unsigned)y * (unsigned)S::N * (unsigned)sizeof(T);
 
@@ -310,7 +312,7 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
             // amplitude gain of the sheet: frozen inversion exp(N/2) (B class),
             // or the class-A saturable gain exp(N / (2 (1 + T1 I)))
             T eh;
-            if constexpr (MODEL == 2) eh = ex((T)0.5 * n * iT1 / (iT1 + I));
+            if constexpr (LS == 2) eh = ex((T)0.5 * n * iT1 / (iT1 + I));
             else eh = ex((T)0.5 * n);
             const T A2 = A[i] * A[i];
             const T aeh = A[i] * eh;
@@ -321,21 +323,17 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
             cx<T> g = scale(e, sqR * aeh);
             // phase of the complex aperture: mirror curvature exp(i k r^2/(2F))
             // as the product of its x and y factors, then the roughness
-            // exp(i psi(x, y)).  One branch per point, as many as a smooth
-            // flat mirror needs; hoisting these loads out of the point loop
-            // costs registers.
-            if (phased) {
-                if (foc) g = cmul(g, cmul(gld<cx<T>>(foc, (unsigned)sizeof(cx<T>) * x), fy));
-                if (rough) g = cmul(g, gld<cx<T>>(rough, 2u * row + (unsigned)sizeof(cx<T>) * x));
-            }
+            // exp(i psi(x, y)) (compiled in for the roughness kernels only)
+            if (foc) g = cmul(g, cmul(gld<cx<T>>(foc, (unsigned)sizeof(cx<T>) * x), fy));
+            if constexpr (ROUGH) g = cmul(g, gld<cx<T>>(rough, 2u * row + (unsigned)sizeof(cx<T>) * x));
             v[i] = g;
             if constexpr (MODE != ROW_DIAG) {
                 const T pump = pc ? N0 * fma_(mamp * gld<T>(pc, (unsigned)sizeof(T) * x), pcy, (T)1) : N0;
                 T nn;
-                if constexpr (MODEL == 0) {
+                if constexpr (LS == 0) {
                     // forward Euler over one trip
                     nn = fma_(-n, I, fma_(pump - n, iT1, n));
-                } else if constexpr (MODEL == 1) {
+                } else if constexpr (LS == 1) {
                     // exact over one trip with I frozen: relax to N_eq at rate 1/T1 + I
                     const T neq = pump * iT1 / (iT1 + I);
                     nn = fma_(n - neq, ex(-(iT1 + I)), neq);

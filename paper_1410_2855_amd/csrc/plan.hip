@@ -223,6 +223,7 @@ static CavDesc sheet_desc(const lsr_plan_s* p, void* E, void* Ninv, int k) {
         d.mask = nullptr;
         d.foc = nullptr;
         d.rough = nullptr;
+        d.model &= MODEL_MASK;
     }
     return d;
 }
@@ -419,7 +420,7 @@ int lsr_plan_set_model(lsr_plan p, int model) {
     if (!p) return set_err(LSR_EINVAL, "plan is NULL");
     if (model < LSR_MODEL_B_EULER || model > LSR_MODEL_CLASS_A) return set_err(LSR_EINVAL, "model %d out of range", model);
     p->model = model;
-    p->d.model = model;
+    p->d.model = model | (p->d_rough ? MODEL_ROUGH : 0);
     ++p->version;
     return LSR_OK;
 }
@@ -484,6 +485,7 @@ int lsr_plan_set_roughness(lsr_plan p, const double* psi) {
     if (p->d_rough) (void)hipFree(p->d_rough);
     p->d_rough = t;
     p->d.rough = t;
+    p->d.model = p->model | (t ? MODEL_ROUGH : 0);
     ++p->version;
     return LSR_OK;
 }

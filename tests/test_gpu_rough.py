@@ -158,9 +158,13 @@ def test_diag_includes_the_roughness():
     assert d["dominant_bin"] == dom
 
 
+@pytest.mark.parametrize("models", [False, True])
 @pytest.mark.parametrize("engine", [0, 1, 2])
-def test_rough_cavities_in_a_batch_are_the_plain_path_bitwise(engine):
-    cavs = [c.with_(rough_rms=0.6 if i % 2 else 0.0) for i, c in enumerate(sweep(6, seed=5, sizes=(256, 512, 1024)))]
+def test_rough_cavities_in_a_batch_are_the_plain_path_bitwise(engine, models):
+    """Rough and smooth cavities in one batch (with models: every local-step
+    model, rough or not) advance exactly as each alone."""
+    cavs = [c.with_(rough_rms=0.6 if i % 2 else 0.0, model=(i // 2) % 3 if models else 0)
+            for i, c in enumerate(sweep(6, seed=5, sizes=(256, 512, 1024)))]
     trips = 9
 
     def fresh():
