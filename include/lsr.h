@@ -192,7 +192,8 @@ int lsr_plan_set_slices(lsr_plan p, int m);
  * (8 B per point, 16 for FP64 plans) and applies it in the local step at the
  * mirror sheet: the row pass then reads that many more bytes per point.
  * Rough plans run on kernels compiled with the roughness factor (the default
- * kernels carry none); a batch holding the plan regroups on its next call,
+ * kernels carry none); a batch holding the plan regroups on its next call
+ * (sizes with a rough cavity run on kernels that read each cavity's code),
  * as after a model change.  Waits for the plan's stream and allocates the
  * table (the previous one is freed).  Diagnostics (lsr_diag) include it.
  * LSR_EINVAL for a non-finite psi. */

@@ -33,6 +33,13 @@ GroupInfo group_any_768();
 GroupInfo group_any_1024();
 GroupInfo group_any_2048();
 GroupInfo group_any_4096();
+GroupInfo group_anyr_256();
+GroupInfo group_anyr_384();
+GroupInfo group_anyr_512();
+GroupInfo group_anyr_768();
+GroupInfo group_anyr_1024();
+GroupInfo group_anyr_2048();
+GroupInfo group_anyr_4096();
 
 static const std::vector<GroupInfo>& groups() {
     static const std::vector<GroupInfo> g = {group_256(),  group_384(),  group_512(),
@@ -41,7 +48,9 @@ static const std::vector<GroupInfo>& groups() {
                                              group_1024r(), group_1024t(), group_2048r(),
                                              group_any_256(), group_any_384(), group_any_512(),
                                              group_any_768(), group_any_1024(), group_any_2048(),
-                                             group_any_4096()};
+                                             group_any_4096(), group_anyr_256(), group_anyr_384(),
+                                             group_anyr_512(), group_anyr_768(), group_anyr_1024(),
+                                             group_anyr_2048(), group_anyr_4096()};
     return g;
 }
 int group_count() { return (int)groups().size(); }
@@ -280,32 +289,35 @@ static int batch_pack(lsr_batch_s* b) {
 // alternative plan) and packs their task lists.
 static int batch_partition(lsr_batch_s* b) {
     groups_free(b);
-    // sizes with a cavity of another local-step code than the default (another
-    // model, or a rough mirror) run on kernels that read each cavity's code
-    // (key -N, one group per size)
+    // sizes with a cavity of another local-step code than the default run on
+    // kernels that read each cavity's code, one group per size: level 1 for
+    // other models, 2 when a cavity of that size has a rough mirror (key
+    // -(4N + level))
     b->models.clear();
-    std::map<int, bool> other_model;
+    std::map<int, int> level;
     for (auto* q : b->plans) {
         b->models.push_back(q->d.model);
-        other_model[q->N] = other_model[q->N] || q->d.model != 0;
+        const int l = (q->d.model & MODEL_ROUGH) ? 2 : q->d.model != 0 ? 1 : 0;
+        level[q->N] = std::max(level[q->N], l);
     }
     std::map<int, std::vector<int>> parts;
     for (int i = 0; i < (int)b->plans.size(); ++i) {
         ShapeInfo s;
         shape_for(b->plans[i]->N, false, &s);
         const int N = b->plans[i]->N;
-        parts[other_model[N] ? -N : b->tune.merge ? s.threads : N].push_back(i);
+        parts[level[N] ? -(4 * N + level[N]) : b->tune.merge ? s.threads : N].push_back(i);
     }
     for (auto& kv : parts) {
         const GroupInfo* best = nullptr;
         const bool any = kv.first < 0;
+        const int any_level = any ? (-kv.first) % 4 : 0;
         const bool merged = b->tune.merge && !any;
-        const int key = any ? -kv.first : kv.first;
+        const int key = any ? (-kv.first) / 4 : kv.first;
         const int want = (merged || any) ? 0 : b->tune.shape;
         for (int pass = 0; pass < 2 && !best; ++pass)
         for (int gi = 0; gi < group_count() && !best; ++gi) {
             const GroupInfo* g = group_at(gi);
-            if (g->any_model != (any ? 1 : 0)) continue;
+            if (g->any_model != any_level) continue;
             if (merged ? g->threads != key : (g->nsizes != 1 || g->sizes[0] != key)) continue;
             // the wanted plan first, else the default one
             if (g->alt != (pass == 0 ? want : 0)) continue;
@@ -448,9 +460,13 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
         std::vector<CavDesc> h;
         for (int c : g.cav) {
             CavDesc d = b->plans[c]->d;
-            // the roughness kernels read d.rough without a check
+            // the roughness kernels read d.rough without a check; a group runs
+            // only the local-step codes it was compiled for
             if (((d.model & MODEL_ROUGH) != 0) != (d.rough != nullptr))
                 return set_err(LSR_EINVAL, "cavity %d: roughness code and table disagree", c);
+            const int need = (d.model & MODEL_ROUGH) ? 2 : d.model != 0 ? 1 : 0;
+            if (need > g.g->any_model)
+                return set_err(LSR_EINVAL, "cavity %d: local-step code %d not in its group", c, d.model);
             d.E = E[c];
             d.Ninv = N[c];
             if (g.d_tw) d.tw = g.d_tw;

@@ -41,7 +41,8 @@ struct GroupInfo {
     int sizes[8];
     ShapeInfo shapes[8];   // the FFT plan of each size
     int alt;               // 0: the sizes' default plans; k > 0: alternative plan k
-    int any_model;         // 1: each cavity's own local-step model; 0: the default one
+    int any_model;         // 0: the default local step; 1: each cavity's own local-step
+                           // model; 2: also the mirror roughness
     int nvariants;
     KernelVariant var[4];
 };

@@ -46,8 +46,9 @@ struct Group {
 };
 
 // ANY = 0: the default local step, compiled in; ANY = 1: the cavity's own
-// local-step code (d.model, uniform in a workgroup: the model and whether the
-// mirror roughness applies), one compiled body each.
+// local-step model (d.model, uniform in a workgroup), one compiled body each;
+// ANY = 2: also the roughness bodies (groups holding a rough cavity; the
+// batch puts no rough cavity in the others).
 template <int MODE, int ANY, class S>
 __device__ __forceinline__ bool run_if(const CavDesc& d, int kind, int blk, unsigned char* smem, double* red) {
     if (d.N != S::N) return false;
@@ -57,9 +58,15 @@ __device__ __forceinline__ bool run_if(const CavDesc& d, int kind, int blk, unsi
             switch (d.model) {
             case 1: row_task<S, float, MODE, 1>(d, blk, lds, red); break;
             case 2: row_task<S, float, MODE, 2>(d, blk, lds, red); break;
-            case MODEL_ROUGH + 0: row_task<S, float, MODE, MODEL_ROUGH + 0>(d, blk, lds, red); break;
-            case MODEL_ROUGH + 1: row_task<S, float, MODE, MODEL_ROUGH + 1>(d, blk, lds, red); break;
-            case MODEL_ROUGH + 2: row_task<S, float, MODE, MODEL_ROUGH + 2>(d, blk, lds, red); break;
+            case MODEL_ROUGH + 0:
+                if constexpr (ANY == 2) row_task<S, float, MODE, MODEL_ROUGH + 0>(d, blk, lds, red);
+                break;
+            case MODEL_ROUGH + 1:
+                if constexpr (ANY == 2) row_task<S, float, MODE, MODEL_ROUGH + 1>(d, blk, lds, red);
+                break;
+            case MODEL_ROUGH + 2:
+                if constexpr (ANY == 2) row_task<S, float, MODE, MODEL_ROUGH + 2>(d, blk, lds, red);
+                break;
             default: row_task<S, float, MODE, 0>(d, blk, lds, red); break;
             }
         } else {
