@@ -207,3 +207,30 @@ def test_rough_cavities_in_a_batch_are_the_plain_path_bitwise(engine, models):
     lsr.lsr_batch_destroy(b)
     for p in plans:
         p.close()
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+def test_rough_cavities_of_every_size_in_a_batch_are_the_plain_path_bitwise(engine):
+    """The roughness batch kernels of the sizes not covered above."""
+    cavs = [Cavity(N=N, F=300.0, R=0.9, pump_ratio=2.5, T1=400.0, index=70 + i, rough_rms=0.7 if i % 2 == 0 else 0.0,
+                   model=i % 3) for i, N in enumerate((384, 768, 2048, 4096, 768))]
+    trips = 3
+    plans = [lsr.Plan(c) for c in cavs]
+    st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+    ref = []
+    for p, (e, n) in zip(plans, st):
+        e2, n2 = e.clone(), n.clone()
+        p.roundtrips(e2, n2, trips)
+        p.sync()
+        ref.append((e2, n2))
+    Es, Ns = [s[0] for s in st], [s[1] for s in st]
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_configure(b, engine=engine, shape=0)
+    lsr.lsr_batch_roundtrips(b, Es, Ns, trips)
+    for p in plans:
+        p.sync()
+    for i in range(len(cavs)):
+        assert torch.equal(Es[i], ref[i][0]) and torch.equal(Ns[i], ref[i][1]), cavs[i].N
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
