@@ -169,3 +169,20 @@ def test_pack_tasks_orders_dependencies(sizes, lag):
             assert seen_rows.get(c, 0) == nrb[c], "column task before all rows of its cavity"
     with pytest.raises(lsr.LsrError):
         lsr.lsr_pack_tasks([1000])
+
+
+def test_missing_library_fails_loudly():
+    """No fallback: without liblsr.so the binding raises instead of computing
+    anything (fresh interpreter, so nothing is cached)."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_1410_2855_amd import lsr\n"
+            "try:\n"
+            "    lsr.load('/nonexistent/liblsr.so')\n"
+            "except ImportError as e:\n"
+            "    print('IMPORT_ERROR', e)\n"
+            "    raise SystemExit(3)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 3 and "IMPORT_ERROR" in r.stdout and "not built" in r.stdout
