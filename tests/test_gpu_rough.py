@@ -234,3 +234,35 @@ def test_rough_cavities_of_every_size_in_a_batch_are_the_plain_path_bitwise(engi
     lsr.lsr_batch_destroy(b)
     for p in plans:
         p.close()
+
+
+def test_autotune_with_rough_cavities_keeps_results(tmp_path):
+    """The tuner re-partitions a batch holding rough and smooth cavities for
+    every engine and plan it times; whatever it keeps, the rough cavities
+    (always on the default plans) stay bitwise the one-cavity path and the
+    smooth ones within rounding of it."""
+    cavs = [c.with_(rough_rms=0.5 if i % 2 else 0.0) for i, c in enumerate(sweep(4, seed=11, sizes=(256, 512)))]
+    trips = 9
+    plans = [lsr.Plan(c) for c in cavs]
+    st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+    ref = []
+    for p, (e, n) in zip(plans, st):
+        e2, n2 = e.clone(), n.clone()
+        p.roundtrips(e2, n2, trips)
+        p.sync()
+        ref.append((e2, n2))
+    Es, Ns = [s[0] for s in st], [s[1] for s in st]
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_autotune(None, b, str(tmp_path / "tune.json"))
+    cfg = lsr.lsr_batch_configure(b)
+    lsr.lsr_batch_roundtrips(b, Es, Ns, trips)
+    for p in plans:
+        p.sync()
+    for i, c in enumerate(cavs):
+        if c.rough_rms or cfg["shape"] == 0:
+            assert torch.equal(Es[i], ref[i][0]) and torch.equal(Ns[i], ref[i][1]), (i, cfg)
+        else:
+            assert rel(Es[i].cpu().numpy(), ref[i][0].cpu().numpy()) <= 2e-6, (i, cfg)
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
