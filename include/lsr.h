@@ -133,8 +133,9 @@ int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L,
  *                    pump, N' = P.
  * The trace and diagnostics sums use the model's gain factor in place of
  * exp(N).  Takes effect on the next call, also in batches holding the plan
- * (a batch regroups its cavities when a model changes: sizes with a cavity
- * of another model run on kernels that read each cavity's model).
+ * (a batch regroups its cavities when a model changes: a size whose
+ * cavities all have one other model runs on kernels compiled for it, a size
+ * with mixed models on kernels that read each cavity's model).
  * LSR_EINVAL for an unknown model. */
 typedef enum { LSR_MODEL_B_EULER = 0, LSR_MODEL_B_EXACT = 1, LSR_MODEL_CLASS_A = 2 } lsr_model;
 int lsr_plan_set_model(lsr_plan p, int model);

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -40,6 +41,20 @@ GroupInfo group_anyr_768();
 GroupInfo group_anyr_1024();
 GroupInfo group_anyr_2048();
 GroupInfo group_anyr_4096();
+GroupInfo group_fix1_256();
+GroupInfo group_fix2_256();
+GroupInfo group_fix1_384();
+GroupInfo group_fix2_384();
+GroupInfo group_fix1_512();
+GroupInfo group_fix2_512();
+GroupInfo group_fix1_768();
+GroupInfo group_fix2_768();
+GroupInfo group_fix1_1024();
+GroupInfo group_fix2_1024();
+GroupInfo group_fix1_2048();
+GroupInfo group_fix2_2048();
+GroupInfo group_fix1_4096();
+GroupInfo group_fix2_4096();
 
 static const std::vector<GroupInfo>& groups() {
     static const std::vector<GroupInfo> g = {group_256(),  group_384(),  group_512(),
@@ -50,7 +65,8 @@ static const std::vector<GroupInfo>& groups() {
                                              group_any_768(), group_any_1024(), group_any_2048(),
                                              group_any_4096(), group_anyr_256(), group_anyr_384(),
                                              group_anyr_512(), group_anyr_768(), group_anyr_1024(),
-                                             group_anyr_2048(), group_anyr_4096()};
+                                             group_anyr_2048(), group_anyr_4096(),
+                                             group_fix1_256(), group_fix2_256(), group_fix1_384(), group_fix2_384(), group_fix1_512(), group_fix2_512(), group_fix1_768(), group_fix2_768(), group_fix1_1024(), group_fix2_1024(), group_fix1_2048(), group_fix2_2048(), group_fix1_4096(), group_fix2_4096()};
     return g;
 }
 int group_count() { return (int)groups().size(); }
@@ -290,29 +306,34 @@ static int batch_pack(lsr_batch_s* b) {
 static int batch_partition(lsr_batch_s* b) {
     groups_free(b);
     // sizes with a cavity of another local-step code than the default run on
-    // kernels that read each cavity's code, one group per size: level 1 for
-    // other models, 2 when a cavity of that size has a rough mirror (key
-    // -(4N + level))
+    // kernels for that size alone (key -(64N + level)): level ANY_FIXED + m
+    // when every cavity of the size has model m and a smooth mirror, else 1
+    // (kernels that read each cavity's model) or 2 when one has a rough
+    // mirror (model and roughness read per cavity)
     b->models.clear();
     std::map<int, int> level;
+    std::map<int, std::set<int>> codes;
     for (auto* q : b->plans) {
         b->models.push_back(q->d.model);
         const int l = (q->d.model & MODEL_ROUGH) ? 2 : q->d.model != 0 ? 1 : 0;
         level[q->N] = std::max(level[q->N], l);
+        codes[q->N].insert(q->d.model);
     }
+    for (auto& kv : level)
+        if (kv.second == 1 && codes[kv.first].size() == 1) kv.second = ANY_FIXED + *codes[kv.first].begin();
     std::map<int, std::vector<int>> parts;
     for (int i = 0; i < (int)b->plans.size(); ++i) {
         ShapeInfo s;
         shape_for(b->plans[i]->N, false, &s);
         const int N = b->plans[i]->N;
-        parts[level[N] ? -(4 * N + level[N]) : b->tune.merge ? s.threads : N].push_back(i);
+        parts[level[N] ? -(64 * N + level[N]) : b->tune.merge ? s.threads : N].push_back(i);
     }
     for (auto& kv : parts) {
         const GroupInfo* best = nullptr;
         const bool any = kv.first < 0;
-        const int any_level = any ? (-kv.first) % 4 : 0;
+        const int any_level = any ? (-kv.first) % 64 : 0;
         const bool merged = b->tune.merge && !any;
-        const int key = any ? (-kv.first) / 4 : kv.first;
+        const int key = any ? (-kv.first) / 64 : kv.first;
         const int want = (merged || any) ? 0 : b->tune.shape;
         for (int pass = 0; pass < 2 && !best; ++pass)
         for (int gi = 0; gi < group_count() && !best; ++gi) {
@@ -464,9 +485,10 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
             // only the local-step codes it was compiled for
             if (((d.model & MODEL_ROUGH) != 0) != (d.rough != nullptr))
                 return set_err(LSR_EINVAL, "cavity %d: roughness code and table disagree", c);
-            const int need = (d.model & MODEL_ROUGH) ? 2 : d.model != 0 ? 1 : 0;
-            if (need > g.g->any_model)
-                return set_err(LSR_EINVAL, "cavity %d: local-step code %d not in its group", c, d.model);
+            const int lvl = g.g->any_model;
+            const bool runs = lvl >= ANY_FIXED ? d.model == lvl - ANY_FIXED
+                            : lvl == 2 ? true : lvl == 1 ? (d.model & MODEL_ROUGH) == 0 : d.model == 0;
+            if (!runs) return set_err(LSR_EINVAL, "cavity %d: local-step code %d not in its group", c, d.model);
             d.E = E[c];
             d.Ninv = N[c];
             if (g.d_tw) d.tw = g.d_tw;

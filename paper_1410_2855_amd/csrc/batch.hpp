@@ -8,6 +8,10 @@
 
 namespace lsr {
 
+// Group kernels compiled for one local-step model m alone carry the code
+// ANY_FIXED + m (see GroupInfo::any_model).
+enum : int { ANY_FIXED = 16 };
+
 enum : int { TASK_ROW = 0, TASK_COL = 1 };
 
 // Control block of a group (device, unsigned words).
@@ -42,7 +46,8 @@ struct GroupInfo {
     ShapeInfo shapes[8];   // the FFT plan of each size
     int alt;               // 0: the sizes' default plans; k > 0: alternative plan k
     int any_model;         // 0: the default local step; 1: each cavity's own local-step
-                           // model; 2: also the mirror roughness
+                           // model; 2: also the mirror roughness; ANY_FIXED + m: model m
+                           // alone
     int nvariants;
     KernelVariant var[4];
 };

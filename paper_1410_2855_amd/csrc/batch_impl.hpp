@@ -48,13 +48,17 @@ struct Group {
 // ANY = 0: the default local step, compiled in; ANY = 1: the cavity's own
 // local-step model (d.model, uniform in a workgroup), one compiled body each;
 // ANY = 2: also the roughness bodies (groups holding a rough cavity; the
-// batch puts no rough cavity in the others).
+// batch puts no rough cavity in the others).  ANY = ANY_FIXED + m: model m
+// alone, compiled in (groups whose cavities all have model m and a smooth
+// mirror; no switch, so no registers of the other bodies).
 template <int MODE, int ANY, class S>
 __device__ __forceinline__ bool run_if(const CavDesc& d, int kind, int blk, unsigned char* smem, double* red) {
     if (d.N != S::N) return false;
     cx<float>* lds = reinterpret_cast<cx<float>*>(smem);
     if (kind == TASK_ROW) {
-        if constexpr (ANY && MODE != ROW_LAST) {
+        if constexpr (ANY >= ANY_FIXED && MODE != ROW_LAST) {
+            row_task<S, float, MODE, ANY - ANY_FIXED>(d, blk, lds, red);
+        } else if constexpr (ANY && MODE != ROW_LAST) {
             switch (d.model) {
             case 1: row_task<S, float, MODE, 1>(d, blk, lds, red); break;
             case 2: row_task<S, float, MODE, 2>(d, blk, lds, red); break;

@@ -1,0 +1,9 @@
+// Batch kernels for N = 384 cavities that all have the same non-default
+// local-step model (exact B-class update or class A) and a smooth mirror:
+// that model alone is compiled in.
+#include "batch_impl.hpp"
+
+namespace lsr {
+GroupInfo group_fix1_384() { return group_info<S384>({GroupKernelsT<2, ANY_FIXED + 1, S384>::variant(), GroupKernelsT<3, ANY_FIXED + 1, S384>::variant()}, 0, ANY_FIXED + 1); }
+GroupInfo group_fix2_384() { return group_info<S384>({GroupKernelsT<2, ANY_FIXED + 2, S384>::variant(), GroupKernelsT<3, ANY_FIXED + 2, S384>::variant()}, 0, ANY_FIXED + 2); }
+}  // namespace lsr

@@ -1,0 +1,9 @@
+// Batch kernels for N = 512 cavities that all have the same non-default
+// local-step model (exact B-class update or class A) and a smooth mirror:
+// that model alone is compiled in.
+#include "batch_impl.hpp"
+
+namespace lsr {
+GroupInfo group_fix1_512() { return group_info<S512>({GroupKernelsT<2, ANY_FIXED + 1, S512>::variant(), GroupKernelsT<3, ANY_FIXED + 1, S512>::variant()}, 0, ANY_FIXED + 1); }
+GroupInfo group_fix2_512() { return group_info<S512>({GroupKernelsT<2, ANY_FIXED + 2, S512>::variant(), GroupKernelsT<3, ANY_FIXED + 2, S512>::variant()}, 0, ANY_FIXED + 2); }
+}  // namespace lsr

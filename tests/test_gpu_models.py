@@ -130,3 +130,48 @@ def test_batched_models_match_the_oracle():
     assert ei.value.code == lsr.LSR_EINVAL
     for p in plans:
         p.close()
+
+
+@pytest.mark.parametrize("engine", [1, 0, 2])
+def test_batches_of_one_model_per_size_use_its_own_kernels(engine):
+    """Sizes whose cavities all share one non-default model run on kernels
+    compiled for that model alone; a model change that mixes a size moves it
+    to the kernels that read each cavity's model.  Bitwise the one-cavity
+    path throughout."""
+    cavs = [c.with_(model=1) for c in sweep(3, seed=6, sizes=(512,))]
+    cavs += [c.with_(model=2) for c in sweep(2, seed=7, sizes=(1024,))]
+    cavs += [c.with_(model=1, N=256, index=50 + i) for i, c in enumerate(sweep(2, seed=8, sizes=(256,)))]
+
+    def run(batched):
+        plans = [lsr.Plan(c) for c in cavs]
+        st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+        Es, Ns = [x[0] for x in st], [x[1] for x in st]
+        b = None
+        if batched:
+            b = lsr.lsr_batch_create([p.handle for p in plans])
+            lsr.lsr_batch_configure(b, engine=engine, graph_k=2)
+
+        def go(k):
+            if batched:
+                lsr.lsr_batch_roundtrips(b, Es, Ns, k)
+            else:
+                for p, e, n in zip(plans, Es, Ns):
+                    p.roundtrips(e, n, k)
+
+        go(5)
+        lsr.lsr_plan_set_model(plans[1].handle, lsr.LSR_MODEL_B_EULER)   # 512 becomes mixed
+        lsr.lsr_plan_set_model(plans[3].handle, lsr.LSR_MODEL_B_EXACT)   # 1024 becomes mixed
+        go(4)
+        for p in plans:
+            p.sync()
+        out = [(e.clone(), n.clone()) for e, n in zip(Es, Ns)]
+        if b:
+            lsr.lsr_batch_destroy(b)
+        for p in plans:
+            p.close()
+        return out
+
+    ref = run(False)
+    got = run(True)
+    for i, ((e1, n1), (e2, n2)) in enumerate(zip(ref, got)):
+        assert torch.equal(e1, e2) and torch.equal(n1, n2), i
