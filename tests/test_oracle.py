@@ -282,6 +282,65 @@ def test_energy_balance_identity():
     assert np.allclose(s1[1:] - s1[:-1], (gain - loss - out)[:-1], rtol=1e-9, atol=1e-15 * s1.max())
 
 
+@pytest.mark.parametrize("R", [1.0, 0.8])
+def test_aperture_sum_by_parseval(R):
+    """The trace's S2 = sum |A|^2 |E|^2 pinned on its own (it cancels out of
+    the energy balance): in a cavity without gain (N = N0 = 0) the local step
+    is G = sqrt(R) A E and the propagation is unitary, so the next trip's
+    S1 = sum |E_{n+1}|^2 = sum |G_n|^2 = R S2_n, and with e^N = 1 the output
+    sum S3 equals S2."""
+    lam, L, F = 1.064e-6, 2e-3, 40.0
+    n = 64
+    a = math.sqrt(F * lam * L)
+    p = passive(n, 2 * a / n, lam, L, R=R, ap_kind=1, ap_radius=0.6 * a, ap_order=4)
+    e0 = rand_c((n, n), 21)
+    _, ninv, tr = oracle.run(p, e0, np.zeros((n, n)), 12)
+    s1, s2, s3 = tr[:, 0], tr[:, 1], tr[:, 2]
+    # the aperture removes a sizeable share each trip, so S2 is far from S1
+    assert s2[0] < 0.8 * s1[0]
+    assert np.allclose(s1[1:], R * s2[:-1], rtol=1e-13, atol=0)
+    assert np.allclose(s3, s2, rtol=1e-15, atol=0)
+    assert not ninv.any()
+
+
+def test_aperture_sum_with_a_binary_mask():
+    """With a 0/1 mask as the aperture, S2 is the energy inside the mask:
+    the sum of |E|^2 over the unmasked cells of the incoming field."""
+    n = 32
+    p = passive(n, 1e-5, 1.064e-6, 1e-3, ap_kind=3)
+    mask = (np.random.default_rng(5).random((n, n)) < 0.4).astype(np.float64)
+    p.ap_mask = mask
+    e0 = rand_c((n, n), 22)
+    _, _, tr = oracle.run(p, e0, np.zeros((n, n)), 1)
+    inside = np.abs(e0[mask == 1.0]) ** 2
+    assert abs(tr[0, 1] - math.fsum(inside)) <= 1e-13 * tr[0, 1]
+    assert abs(tr[0, 0] - math.fsum((np.abs(e0) ** 2).ravel())) <= 1e-13 * tr[0, 0]
+
+
+@pytest.mark.parametrize("n,M", [(64, 4), (64, 5), (96, 7)])
+def test_periodic_pump_fourier_content(n, M):
+    """The periodic pump of Sec. 3, N0 (1 + m cos(2 pi x/d) cos(2 pi y/d)) with
+    M periods across the window: with E = 0 and T1 = 1 one trip of the
+    inversion update sets N to the pump map exactly.  On the grid
+    x_j = (j - N/2) dx with d = N dx / M, cos(2 pi x_j / d) =
+    (-1)^M cos(2 pi j M / N), and the two factors' signs cancel, so FFT2 of
+    the map holds N0 N^2 at DC and N0 m N^2 / 4 at each of (+-M, +-M), and
+    nothing else."""
+    lam, L = 1.064e-6, 2e-3
+    dx = 2e-6
+    N0, m = 0.21, 0.3
+    p = CavityParams(N=n, dx=dx, lam=lam, L=L, R=0.9, N0=N0, T1=1.0, ap_kind=0,
+                     mod_amp=m, mod_period=n * dx / M)
+    _, n1, _ = oracle.run(p, np.zeros((n, n), np.complex128), np.full((n, n), 0.05), 1)
+    spec = np.fft.fft2(n1)
+    want = np.zeros((n, n), np.complex128)
+    want[0, 0] = N0 * n * n
+    for ky in (M, n - M):
+        for kx in (M, n - M):
+            want[ky, kx] = N0 * m * n * n / 4
+    assert np.max(np.abs(spec - want)) <= 1e-12 * N0 * n * n
+
+
 def test_inversion_update_pointwise():
     """The second line of Eq. (1) read as the forward-Euler step of Eq. (6):
     N_{n+1} = N_n + (N0 - N_n)/T1 - N_n |E_n|^2, pointwise, with a

@@ -42,6 +42,16 @@ MUTATIONS = [
     ("exact update at the wrong rate", "double rate = 1.0 / p->T1 + I;", "double rate = 1.0 / p->T1;"),
     ("class-A saturation factor", "if (p->model == 2) return exp(0.5 * Nn / (1.0 + p->T1 * I));",
      "if (p->model == 2) return exp(0.5 * Nn / (1.0 + I));"),
+    ("aperture sum over A instead of A^2", "s2 += a2 * I;",
+     "s2 += sqrt(a2) * I;"),
+    ("pump modulation without the N0 factor", "return p->N0 * (1.0 + p->mod_amp * cx * cy);",
+     "return p->N0 + p->mod_amp * cx * cy;"),
+    ("pump period from (N - 1) dx",
+     "double cx = cos(2.0 * M_PI * coord(x, p) / p->mod_period);\n"
+     "    double cy = cos(2.0 * M_PI * coord(y, p) / p->mod_period);",
+     "double dd = p->mod_period * (p->N - 1) / p->N;\n"
+     "    double cx = cos(2.0 * M_PI * coord(x, p) / dd);\n"
+     "    double cy = cos(2.0 * M_PI * coord(y, p) / dd);"),
 ]
 
 
