@@ -19,6 +19,7 @@ import glob
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -160,6 +161,69 @@ def summarize(out_dir: str, workload: str, cavities: int, grid: int, workload_fl
     print(json.dumps(traffic, indent=1))
 
 
+# SQ counter passes (at most 8 SQ counters per rocprofv3 run): WL as above
+SQ_PASSES = {
+    "sqa": "SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE SQ_WAIT_INST_LDS SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
+           "SQ_INSTS_LDS SQ_INSTS_VALU SQ_WAVES GRBM_GUI_ACTIVE",
+    "sqb": "SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VMEM "
+           "SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_WAVE_CYCLES",
+}
+
+
+def sq_commands(workload_flag: str = ""):
+    return {k: "rocprofv3 --pmc %s --output-format csv -d OUT/%s -o %s -- python3 /root/repo/bench.py %s"
+               "--profile --steps 2 --warmup 1" % (v, k, k, workload_flag) for k, v in SQ_PASSES.items()}
+
+
+def summarize_sq(out_dir: str, workload: str, cavities: int, grid: int, workload_flag: str = ""):
+    """profiles/sq_counters_<cavities>x<grid>.txt from the rocprofv3 csv output
+    of the SQ_PASSES runs under OUT: mean per dispatch of the middle-trip form
+    of each pass, and the ratios read from them."""
+    import glob as _g
+
+    vals = {}
+    for tag in SQ_PASSES:
+        files = _g.glob(os.path.join(out_dir, tag, "*counter_collection.csv"))
+        if not files:
+            continue
+        for r in _read_csv(files[0]):
+            for k, pat in PASS_KERNELS.items():
+                if pat in r["Kernel_Name"] and ("Shape<%d," % grid) in r["Kernel_Name"]:
+                    vals.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    cmds = sq_commands(workload_flag)
+    txt = ["SQ counters of the row and column passes: %s" % workload, "",
+           "commands (from /tmp, TMPDIR=/tmp):"] + ["  " + c for c in cmds.values()] + [
+           "values: mean per dispatch of the middle-trip form of each pass (sum over shader engines and XCDs)", ""]
+    for k, cs in vals.items():
+        m = {c: sum(v) / len(v) for c, v in cs.items()}
+        txt.append("%s:" % k)
+        for c in sorted(m):
+            txt.append("  %-24s %16.0f" % (c, m[c]))
+        wc = m.get("SQ_WAVE_CYCLES")
+        if wc:
+            for c, what in (("SQ_WAIT_INST_LDS", "wave cycles waiting on LDS instructions"),
+                            ("SQ_WAIT_ANY", "wave cycles waiting on anything"),
+                            ("SQ_WAIT_INST_ANY", "wave cycles waiting for any instruction issue"),
+                            ("SQ_ACTIVE_INST_VALU", "wave cycles issuing VALU"),
+                            ("SQ_ACTIVE_INST_LDS", "wave cycles issuing LDS"),
+                            ("SQ_ACTIVE_INST_VMEM", "wave cycles issuing vector memory")):
+                if c in m:
+                    txt.append("  share of %-45s %.3f" % (what + ":", m[c] / wc))
+        if "SQ_LDS_BANK_CONFLICT" in m and "SQ_LDS_IDX_ACTIVE" in m:
+            txt.append("  LDS bank-conflict cycles per conflict-free LDS cycle: %.3f"
+                       % (m["SQ_LDS_BANK_CONFLICT"] / max(m["SQ_LDS_IDX_ACTIVE"] - m["SQ_LDS_BANK_CONFLICT"], 1)))
+        if "SQ_INSTS_LDS" in m and "SQ_INSTS_VALU" in m:
+            txt.append("  VALU instructions per LDS instruction: %.1f" % (m["SQ_INSTS_VALU"] / m["SQ_INSTS_LDS"]))
+        if "SQ_WAVES" in m and "SQ_WAVE_CYCLES" in m:
+            txt.append("  wave lifetime (cycles): %.0f" % (m["SQ_WAVE_CYCLES"] / m["SQ_WAVES"]))
+        txt.append("")
+    txt.append("kernel source hash: " + kernel_source_hash())
+    path = os.path.join(ROOT, "profiles", "sq_counters_%dx%d.txt" % (cavities, grid))
+    with open(path, "w") as f:
+        f.write("\n".join(txt) + "\n")
+    print("\n".join(txt))
+
+
 WORKLOADS = {
     "sweep1024": "%d cavities at 1024^2 (sweep parameter draws), FP64-table form",
     "sweep512": "512 cavities, N uniform in {256, 384, 512, 768, 1024} (sweep draws), FP64-table form",
@@ -261,6 +325,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--reps", type=int, default=5,
+                    help="timed calls of --steps round trips each; the reported time is their median")
     ap.add_argument("--cavities", type=int, default=64, help="cavities of the 1024^2 workload")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="sweep1024",
                     help="sweep1024 (default, the metric's configuration): 1024^2 cavities with the sweep's "
@@ -282,12 +348,22 @@ def main():
                     help="short batched run for a profiler, plus a copy kernel of known size")
     ap.add_argument("--summarize", metavar="OUT",
                     help="write profiles/ summaries from rocprofv3 csv output under OUT (no GPU)")
+    ap.add_argument("--summarize-sq", metavar="OUT",
+                    help="write profiles/sq_counters_*.txt from the SQ counter runs under OUT (no GPU)")
     ap.add_argument("--oracle-sizes", action="store_true",
                     help="time the single-threaded FP64 oracle per round trip at every grid size "
                          "(host only, no GPU) and print one JSON line")
     args = ap.parse_args()
     if args.oracle_sizes:
         print(json.dumps(oracle_per_size()), flush=True)
+        return
+    if args.summarize_sq:
+        if args.workload == "sweep1024":
+            summarize_sq(args.summarize_sq, WORKLOADS["sweep1024"] % args.cavities, args.cavities, 1024)
+        elif args.workload == "structured4096":
+            summarize_sq(args.summarize_sq, WORKLOADS["structured4096"], 16, 4096, "--workload structured4096 ")
+        else:
+            sys.exit("--summarize-sq covers the single-size workloads (sweep1024, structured4096)")
         return
     if args.summarize:
         if args.workload == "sweep1024":
@@ -349,13 +425,20 @@ def main():
     def run_batched(k):
         lsr.lsr_batch_roundtrips(batch, Es, Ns, k)
 
-    def timed(fn, steps, warmup):
+    def timed(fn, steps, warmup, reps=1):
+        """Seconds per step: `warmup` untimed steps, then `reps` timed calls of
+        exactly `steps` steps each, every one bracketed by device
+        synchronisation; the median over the calls."""
         fn(warmup)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fn(steps)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
+        per = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn(steps)
+            torch.cuda.synchronize()
+            per.append((time.perf_counter() - t0) / steps)
+        return statistics.median(per), per
 
     if args.profile:
         # calibration copy of known size for the traffic counters: 256 MiB
@@ -363,17 +446,26 @@ def main():
         y = torch.empty_like(x)
         y.copy_(x)
         torch.cuda.synchronize()
-        t = timed(run_batched, args.steps, args.warmup)
+        lsr.lsr_batch_prepare(batch, args.warmup)
+        lsr.lsr_batch_prepare(batch, args.steps)
+        t, _ = timed(run_batched, args.steps, args.warmup)
         print(json.dumps({"profile": True, "ms_per_step": t * 1e3, "config": cfg,
                           "copy_bytes_each_way": x.numel() * 4}), flush=True)
         return
 
-    t_step = timed(run_batched, args.steps, args.warmup)
+    # the graphs a call of `warmup` or `steps` trips replays are captured here,
+    # before any timing
+    lsr.lsr_batch_prepare(batch, args.warmup)
+    lsr.lsr_batch_prepare(batch, args.steps)
+    t_step, t_reps = timed(run_batched, args.steps, args.warmup, args.reps)
     value = pts / t_step
     # dominant kernel: dispatch-timestamp events on the batch's stream, right
     # after the timed batched run (same clocks and cache state)
     row_ms, col_ms, trip_ms = lsr.lsr_batch_time_kernels(batch, Es, Ns, 50)
-    t_plain = timed(run_plain, max(1, args.steps // 4), max(1, args.warmup // 4))
+    # plain one-launch-per-cavity leg: the same trips per call as the batched
+    # leg (at least 20), so the per-call first and last row passes weigh the same
+    plain_steps = max(20, args.steps)
+    t_plain, t_plain_reps = timed(run_plain, plain_steps, max(1, args.warmup), max(3, min(args.reps, 5)))
     plain_value = pts / t_plain
     if cfg["engine"] >= 1:
         # grouped launches (engine 1, or its software-pipelined form 2): one
@@ -408,7 +500,11 @@ def main():
         "config": {"workload": workload,
                    "grid": sorted({c.N for c in cavs}), "cavities": len(cavs), "mode": "batched",
                    "engine": ENGINES.get(cfg["engine"], "?"), "launch": cfg},
-        "plain": {"value": plain_value, "ms_per_step": t_plain * 1e3},
+        "timing": {"reps": len(t_reps), "statistic": "median",
+                   "ms_per_step_each": [round(x * 1e3, 5) for x in t_reps],
+                   "trips_per_call": args.steps},
+        "plain": {"value": plain_value, "ms_per_step": t_plain * 1e3, "trips_per_call": plain_steps,
+                  "reps": len(t_plain_reps)},
         "speedup_batched_vs_plain": value / plain_value,
         "hbm_frac_whole_step": round(pts * (row_bpp + COL_BYTES_PER_PT) / t_step / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,

@@ -238,7 +238,15 @@ int lsr_trace(lsr_plan p, double* out, int capacity);
  * n_trips >= 1 trips; synchronises. */
 int lsr_time_kernels(lsr_plan p, void* E, void* Ninv, int n_trips, double* ms);
 
-/* Diagnostics of the state (E, Ninv); synchronises the stream. */
+/* Diagnostics of the state (E, Ninv), the quantities of lsr_diag_out: the
+ * power leaving through the output mirror, the plane whose transverse
+ * patterns the paper models (abstract), with the gain and aperture balance
+ * of the local step of Eq. (1) and Eq. (12); and the far-field spectrum of
+ * the field leaving the gain sheet, in the spirit of the Fourier images of
+ * Sec. 5, whose dominant transverse wavevector gives the pattern period.  E and Ninv as for
+ * lsr_roundtrips (read only).  Uses the plan's spectrum scratch (allocated
+ * on the first call); synchronises the stream.  LSR_ENONFINITE if the sums
+ * are not finite. */
 int lsr_diag(lsr_plan p, const void* E, const void* Ninv, lsr_diag_out* out);
 
 /* Number of radial spectrum bins of a plan (round(N/sqrt(2)) + 1). */
@@ -257,7 +265,9 @@ void lsr_plan_destroy(lsr_plan p);
  * configuration (FFT plan, engine, register budget, grouping, task-table
  * lag, graph length k) comes from the autotune cache when it holds an entry
  * for this mix of sizes, else from built-in defaults.  The batch runs on
- * the stream of plans[0]. */
+ * the stream its plans are bound to: every plan must be bound to the same
+ * stream (LSR_EINVAL otherwise, here and in every later call that finds a
+ * plan rebound to another one). */
 int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count);
 
 /* Advance cavity i's state (E[i], Ninv[i], laid out as for lsr_roundtrips)
@@ -271,6 +281,28 @@ int lsr_batch_diag(lsr_batch b, int idx, const void* E, const void* Ninv,
 
 /* Set the trips per captured graph (k >= 1; 0 = no graph, eager launches). */
 int lsr_batch_set_graph_trips(lsr_batch b, int k);
+
+/* Capture and instantiate, without running anything, the HIP graphs that a
+ * later lsr_batch_roundtrips call of n_trips >= 0 trips replays, so that the
+ * capture cost is not paid inside that call.  With graph length k > 0 a call
+ * of n <= k + 1 trips replays one graph of the whole call (first row pass,
+ * n - 1 middle trips, last row pass); a longer call runs its first and last
+ * row passes as launches around (n - 1)/k graphs of k middle trips and one
+ * graph of the (n - 1) mod k remaining ones.  A batch keeps up to 8 graphs
+ * and drops the least recently used one (after the stream has drained) when
+ * it needs another; regrouping, repacking or reconfiguring drops them all.
+ * Graphs read the descriptors and task tables from device memory, so new
+ * state pointers or plan parameters need no new capture. */
+int lsr_batch_prepare(lsr_batch b, int n_trips);
+
+/* Failure-path hook for tests of the persistent engine (engine 0): the
+ * column tasks' bounded wait for their cavity's row blocks polls at most
+ * spin_limit times (0 = about 2 s) and waits for extra_need more row blocks
+ * than exist (0 = the real count).  With extra_need > 0 every wait gives up,
+ * every cavity is flagged and its column tasks are skipped; the kernels still
+ * run to completion, and lsr_sync of each plan reports LSR_EDEVICE.  Both
+ * values return to 0 when the batch regroups.  Synchronises. */
+int lsr_batch_test_wait(lsr_batch b, int extra_need, int spin_limit);
 
 /* Launch configuration of a batch; a negative argument keeps the current
  * value.  engine: 0 = one persistent kernel per round trip (task queue with
@@ -290,6 +322,7 @@ int lsr_batch_set_graph_trips(lsr_batch b, int k);
  * path's), k = 1 .. LSR_MAX_SHAPES = alternative plan k of the sizes that
  * have one compiled (others keep their default):
  *   1  reversed radix order: 512 as 16 8 4, 1024 as 16 16 4, 2048 as 16 16 8;
+ *      4096 with 128 lanes per line (32 points per lane, 512 threads);
  *   2  1024 on 8 x 8 tiles, eight lines per workgroup.
  * Every plan computes the same transform; with an alternative plan the
  * batch's results differ from the one-cavity path's only by rounding (they

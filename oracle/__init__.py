@@ -24,6 +24,14 @@ _LIB = os.path.join(_HERE, "liborc.so")
 _lib = None
 
 
+# ORC_SANITIZE=1 builds and loads a separate copy instrumented with
+# AddressSanitizer and UndefinedBehaviorSanitizer (any finding aborts); the
+# process must then preload the ASan runtime.  The arithmetic is unchanged.
+_SANITIZE = os.environ.get("ORC_SANITIZE") == "1"
+if _SANITIZE:
+    _LIB = os.path.join(_HERE, "liborc_san.so")
+
+
 def build(force: bool = False) -> str:
     """Compile ``orc.c`` into ``liborc.so`` with strict IEEE FP64 flags."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
@@ -34,6 +42,8 @@ def build(force: bool = False) -> str:
             "gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math",
             "-ffp-contract=off", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm",
         ]
+        if _SANITIZE:
+            cmd[1:1] = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
     return _LIB

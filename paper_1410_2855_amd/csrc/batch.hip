@@ -27,6 +27,7 @@ GroupInfo group_512r();
 GroupInfo group_1024r();
 GroupInfo group_1024t();
 GroupInfo group_2048r();
+GroupInfo group_4096w();
 GroupInfo group_any_256();
 GroupInfo group_any_384();
 GroupInfo group_any_512();
@@ -60,7 +61,7 @@ static const std::vector<GroupInfo>& groups() {
     static const std::vector<GroupInfo> g = {group_256(),  group_384(),  group_512(),
                                              group_768(),  group_1024(), group_2048(),
                                              group_4096(), group_small(), group_512r(),
-                                             group_1024r(), group_1024t(), group_2048r(),
+                                             group_1024r(), group_1024t(), group_2048r(), group_4096w(),
                                              group_any_256(), group_any_384(), group_any_512(),
                                              group_any_768(), group_any_1024(), group_any_2048(),
                                              group_any_4096(), group_anyr_256(), group_anyr_384(),
@@ -226,8 +227,16 @@ struct lsr_batch_s {
     std::vector<int> models;         // the plans' local-step codes (model, roughness) when grouped
     Tune tune;
     std::string key;
-    hipGraphExec_t graph = nullptr;
-    int graph_trips = 0;
+    // captured launch sequences, reused across calls (see run_trips)
+    struct Graph {
+        int kind = 0;                    // GRAPH_MID or GRAPH_CALL
+        int len = 0;                     // trips
+        hipGraphExec_t exec = nullptr;
+        unsigned long long used = 0;     // last use (for eviction)
+    };
+    std::vector<Graph> graphs;
+    unsigned long long graph_clock = 0;
+    bool launched = false;               // a graph may still be in flight on stream
 };
 
 static void groups_free(lsr_batch_s* b) {
@@ -244,8 +253,10 @@ static void groups_free(lsr_batch_s* b) {
     b->lastN.clear();
 }
 
+static void drop_graphs(lsr_batch_s* b);
+
 static void batch_free(lsr_batch_s* b) {
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    drop_graphs(b);
     groups_free(b);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -419,7 +430,7 @@ static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind, LaunchEvents 
     return LSR_OK;
 }
 
-static int launch_trip(lsr_batch_s* b, int mode, LaunchEvents ev = {}) {
+static int launch_trip(lsr_batch_s* b, int mode, LaunchEvents ev) {
     if (b->tune.engine >= 1) {
         // grouped: every cavity's row blocks, then every cavity's column blocks
         int rc = launch_grouped_pass(b, mode, TASK_ROW);
@@ -442,32 +453,78 @@ static int launch_trip(lsr_batch_s* b, int mode, LaunchEvents ev = {}) {
     return LSR_OK;
 }
 
-static void drop_graph(lsr_batch_s* b) {
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
-    b->graph = nullptr;
-    b->graph_trips = 0;
+// Graph kinds: GRAPH_MID holds `len` middle round trips (tiled state in and
+// out); GRAPH_CALL a whole call of `len` trips: the first row pass (row-major
+// state in), len - 1 middle trips, the last row pass (row-major state out).
+enum : int { GRAPH_MID = 0, GRAPH_CALL = 1 };
+static constexpr size_t kMaxGraphs = 8;
+
+// Destroy every captured graph (after the ones in flight have finished: the
+// task tables and descriptors they read may be replaced next).
+static void drop_graphs(lsr_batch_s* b) {
+    if (b->graphs.empty()) return;
+    if (b->launched && b->stream) (void)hipStreamSynchronize(b->stream);
+    for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+    b->launched = false;
 }
 
-static int ensure_graph(lsr_batch_s* b, int k) {
-    if (b->graph && b->graph_trips == k) return LSR_OK;
-    drop_graph(b);
+static int launch_trip(lsr_batch_s* b, int mode, LaunchEvents ev);
+
+// The graph of (kind, len), captured on the batch's private stream on first
+// use.  Graphs read the descriptors and task tables from device memory, so a
+// graph stays valid until the batch regroups or repacks (drop_graphs).
+static int get_graph(lsr_batch_s* b, int kind, int len, hipGraphExec_t* out) {
+    for (auto& g : b->graphs)
+        if (g.kind == kind && g.len == len) {
+            g.used = ++b->graph_clock;
+            *out = g.exec;
+            return LSR_OK;
+        }
+    if (b->graphs.size() >= kMaxGraphs) {
+        // evict the least recently used graph once nothing is in flight
+        if (b->launched) LSR_HIP(hipStreamSynchronize(b->stream));
+        b->launched = false;
+        size_t lru = 0;
+        for (size_t i = 1; i < b->graphs.size(); ++i)
+            if (b->graphs[i].used < b->graphs[lru].used) lru = i;
+        (void)hipGraphExecDestroy(b->graphs[lru].exec);
+        b->graphs.erase(b->graphs.begin() + (long)lru);
+    }
     hipGraph_t gr = nullptr;
     LSR_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     int rc = LSR_OK;
-    for (int t = 0; t < k && rc == LSR_OK; ++t) rc = launch_trip(b, ROW_MID);
+    if (kind == GRAPH_CALL) {
+        rc = launch_trip(b, ROW_FIRST, {});
+        for (int t = 1; t < len && rc == LSR_OK; ++t) rc = launch_trip(b, ROW_MID, {});
+        if (rc == LSR_OK) rc = launch_trip(b, ROW_LAST, {});
+    } else {
+        for (int t = 0; t < len && rc == LSR_OK; ++t) rc = launch_trip(b, ROW_MID, {});
+    }
     const hipError_t e = hipStreamEndCapture(b->stream, &gr);
     if (rc != LSR_OK) {
         if (gr) (void)hipGraphDestroy(gr);
         return rc;
     }
     if (e != hipSuccess) return set_err(LSR_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    const hipError_t ie = hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0);
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
     (void)hipGraphDestroy(gr);
-    if (ie != hipSuccess) {
-        b->graph = nullptr;
-        return set_err(LSR_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
-    }
-    b->graph_trips = k;
+    if (ie != hipSuccess) return set_err(LSR_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
+    lsr_batch_s::Graph g;
+    g.kind = kind;
+    g.len = len;
+    g.exec = ex;
+    g.used = ++b->graph_clock;
+    b->graphs.push_back(g);
+    *out = ex;
+    return LSR_OK;
+}
+
+static int graph_launch(lsr_batch_s* b, hipGraphExec_t ex) {
+    if (hipGraphLaunch(ex, b->stream) != hipSuccess)
+        return set_err(LSR_EDEVICE, "graph launch failed: %s", hipGetErrorString(hipGetLastError()));
+    b->launched = true;
     return LSR_OK;
 }
 
@@ -512,28 +569,51 @@ static int regroup_if_models_changed(lsr_batch_s* b) {
     for (size_t i = 0; same && i < b->plans.size(); ++i) same = b->models[i] == b->plans[i]->d.model;
     if (same) return LSR_OK;
     LSR_HIP(hipStreamSynchronize(b->stream));
-    drop_graph(b);
+    drop_graphs(b);
     return batch_partition(b);
 }
 
-static int run_trips(lsr_batch_s* b, int n) {
-    int rc = launch_trip(b, ROW_FIRST);
-    int left = n - 1;
+// The launches of a call of n >= 1 trips.  With graphs (graph_k = k > 0): a
+// call of n <= k + 1 trips replays one graph of the whole call; a longer call
+// runs its first row pass, (n - 1) / k graphs of k trips, one graph of the
+// remaining trips and its last row pass.  prepare_only captures and
+// instantiates the graphs without launching anything.
+static int run_trips(lsr_batch_s* b, int n, bool prepare_only = false) {
     const int k = b->tune.graph_k;
-    if (rc == LSR_OK && k > 0 && left >= k) {
-        rc = ensure_graph(b, k);
-        while (rc == LSR_OK && left >= k) {
-            if (hipGraphLaunch(b->graph, b->stream) != hipSuccess)
-                rc = set_err(LSR_EDEVICE, "graph launch failed: %s", hipGetErrorString(hipGetLastError()));
-            left -= k;
-        }
+    hipGraphExec_t ex = nullptr;
+    if (k <= 0) {
+        if (prepare_only) return LSR_OK;
+        int rc = launch_trip(b, ROW_FIRST, {});
+        for (int t = 1; t < n && rc == LSR_OK; ++t) rc = launch_trip(b, ROW_MID, {});
+        if (rc == LSR_OK) rc = launch_trip(b, ROW_LAST, {});
+        return rc;
     }
-    while (rc == LSR_OK && left > 0) {
-        rc = launch_trip(b, ROW_MID);
-        --left;
+    if (n - 1 <= k) {
+        int rc = get_graph(b, GRAPH_CALL, n, &ex);
+        return rc != LSR_OK || prepare_only ? rc : graph_launch(b, ex);
     }
-    if (rc == LSR_OK) rc = launch_trip(b, ROW_LAST);
+    const int q = (n - 1) / k, r = (n - 1) % k;
+    hipGraphExec_t ek = nullptr, er = nullptr;
+    int rc = get_graph(b, GRAPH_MID, k, &ek);
+    if (rc == LSR_OK && r > 0) rc = get_graph(b, GRAPH_MID, r, &er);
+    if (rc != LSR_OK || prepare_only) return rc;
+    rc = launch_trip(b, ROW_FIRST, {});
+    for (int i = 0; i < q && rc == LSR_OK; ++i) rc = graph_launch(b, ek);
+    if (rc == LSR_OK && r > 0) rc = graph_launch(b, er);
+    if (rc == LSR_OK) rc = launch_trip(b, ROW_LAST, {});
     return rc;
+}
+
+// A batch orders its work after the caller's work on the stream its plans
+// share, and the plans' own synchronising calls (lsr_sync, lsr_trace, the
+// table-replacing setters) wait on that stream: every plan must be bound to
+// the same stream, also after lsr_plan_set_stream.
+static int check_streams(lsr_batch_s* b) {
+    for (size_t i = 1; i < b->plans.size(); ++i)
+        if (b->plans[i]->stream != b->plans[0]->stream)
+            return set_err(LSR_EINVAL, "plan %zu is bound to another stream than plan 0", i);
+    b->user = b->plans[0]->stream;
+    return LSR_OK;
 }
 
 extern "C" {
@@ -571,6 +651,8 @@ int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count) {
             return set_err(LSR_EUNSUPPORTED, "plan %d: batches run single-sheet plans only", i);
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return set_err(LSR_EINVAL, "plan %d appears twice", i);
+        if (plans[i]->stream != plans[0]->stream)
+            return set_err(LSR_EINVAL, "plan %d is bound to another stream than plan 0", i);
     }
     lsr_batch_s* b = new (std::nothrow) lsr_batch_s();
     if (!b) return set_err(LSR_ENOMEM, "host allocation failed");
@@ -603,9 +685,28 @@ int lsr_batch_set_graph_trips(lsr_batch b, int k) {
     if (!b || k < 0) return set_err(LSR_EINVAL, "bad batch or k");
     if (k != b->tune.graph_k) {
         DeviceGuard dg(b->device);
-        drop_graph(b);
+        drop_graphs(b);
         b->tune.graph_k = k;
     }
+    return LSR_OK;
+}
+
+int lsr_batch_prepare(lsr_batch b, int n_trips) {
+    if (!b || n_trips < 0) return set_err(LSR_EINVAL, "bad batch or n_trips");
+    if (n_trips == 0) return LSR_OK;
+    DeviceGuard dg(b->device);
+    int rc = regroup_if_models_changed(b);
+    if (rc == LSR_OK) rc = run_trips(b, n_trips, true);
+    return rc;
+}
+
+int lsr_batch_test_wait(lsr_batch b, int extra_need, int spin_limit) {
+    if (!b || extra_need < 0 || spin_limit < 0) return set_err(LSR_EINVAL, "bad batch or test setting");
+    DeviceGuard dg(b->device);
+    LSR_HIP(hipStreamSynchronize(b->stream));
+    const unsigned w[2] = {(unsigned)spin_limit, (unsigned)extra_need};
+    static_assert(CTRL_EXTRA == CTRL_SPIN + 1, "adjacent control words");
+    for (auto& g : b->grp) LSR_HIP(hipMemcpy(g.d_ctrl + CTRL_SPIN, w, sizeof w, hipMemcpyHostToDevice));
     return LSR_OK;
 }
 
@@ -626,7 +727,7 @@ int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, in
     if (shape >= 0) t.shape = shape;
     const bool regroup = t.merge != b->tune.merge || t.shape != b->tune.shape;
     const bool repack = t.lag != b->tune.lag;
-    drop_graph(b);
+    drop_graphs(b);
     b->tune = t;
     if (regroup || repack) {
         LSR_HIP(hipStreamSynchronize(b->stream));
@@ -656,6 +757,7 @@ int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* N, int n_trip
         if (b->plans[i]->slices != 1)
             return set_err(LSR_EUNSUPPORTED, "plan %zu: batches run single-sheet plans only", i);
     }
+    if (check_streams(b)) return LSR_EINVAL;
     if (n_trips == 0) return LSR_OK;
     DeviceGuard dg(b->device);
     // order after the caller's work on the plans' stream, and back
@@ -677,6 +779,7 @@ int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* N, int n_trip
 int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* N, int n_trips, double* ms) {
     if (!b || !ms || !E || !N) return set_err(LSR_EINVAL, "bad arguments");
     if (n_trips < 1) return set_err(LSR_EINVAL, "n_trips < 1");
+    if (check_streams(b)) return LSR_EINVAL;
     DeviceGuard dg(b->device);
     LSR_HIP(hipEventRecord(b->ev_in, b->user));
     LSR_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
@@ -750,8 +853,9 @@ void lsr_batch_destroy(lsr_batch b) {
 // state; returns ms per trip or a negative status.
 static double time_batch(lsr_batch_s* b, const std::vector<void*>& E, const std::vector<void*>& N, int trips) {
     if (upload_descs(b, E.data(), N.data(), false)) return -1;
-    // warm-up; with graphs long enough to build the graph outside the timing
-    if (run_trips(b, b->tune.graph_k > 0 ? b->tune.graph_k + 2 : 2)) return -1;
+    // warm-up with the timed call's length: its graphs are captured here,
+    // outside the timing
+    if (run_trips(b, trips)) return -1;
     hipEvent_t t0, t1;
     if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return -1;
     (void)hipEventRecord(t0, b->stream);
@@ -809,7 +913,7 @@ int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
     for (auto& kv : by_threads) mixed |= kv.second.size() > 1;
     auto consider = [&](const Tune& t, int n) {
         b->tune = t;
-        drop_graph(b);
+        drop_graphs(b);
         if (batch_pack(b)) return;
         const double ms = time_batch(b, E, N, n);
         if (ms > 0 && ms < best_ms) {
@@ -874,7 +978,7 @@ int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
     for (int k : {0, 4, 16, 64}) {
         b->tune = best;
         b->tune.graph_k = k;
-        drop_graph(b);
+        drop_graphs(b);
         if (batch_pack(b)) continue;
         const double ms = time_batch(b, E, N, std::max(trips, k));
         if (ms > 0 && ms < best_ms * 0.995) {
@@ -885,7 +989,7 @@ int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
     (void)hipStreamSynchronize(b->stream);
     release();
     b->tune = best;
-    drop_graph(b);
+    drop_graphs(b);
     b->lastE.clear();
     b->lastN.clear();
     int rc = batch_pack(b);

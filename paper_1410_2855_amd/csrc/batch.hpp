@@ -15,7 +15,12 @@ enum : int { ANY_FIXED = 16 };
 enum : int { TASK_ROW = 0, TASK_COL = 1 };
 
 // Control block of a group (device, unsigned words).
-enum : int { CTRL_HEAD = 0, CTRL_EXIT = 1, CTRL_NCAV = 2, CTRL_ABORT = 3, CTRL_ROWDONE = 16 };
+// CTRL_SPIN and CTRL_EXTRA are set by the host only (zero by default): the
+// column tasks' poll limit (0 = about 2 s) and a count added to the row
+// blocks a column task waits for (a nonzero value makes every wait give up:
+// the failure path, exercised from the host).
+enum : int { CTRL_HEAD = 0, CTRL_EXIT = 1, CTRL_NCAV = 2, CTRL_ABORT = 3, CTRL_SPIN = 4, CTRL_EXTRA = 5,
+             CTRL_ROWDONE = 16 };
 
 // Optional timestamps of one dispatch: when either event is set the launch
 // goes through hipExtLaunchKernelGGL, which records the kernel's own start

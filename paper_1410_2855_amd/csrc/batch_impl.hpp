@@ -91,6 +91,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
     __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
     __shared__ double red[4 * 16];
     __shared__ int s_ticket;
+    __shared__ int s_ok;
     unsigned* head = ctrl + CTRL_HEAD;
     unsigned* done = ctrl + CTRL_ROWDONE;
     for (;;) {
@@ -106,11 +107,13 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
             const int kind = __builtin_amdgcn_readfirstlane(tk.y);
             const int blk = __builtin_amdgcn_readfirstlane(tk.z);
             const CavDesc& d = descs[cav];
+            bool run = true;
             if (kind == TASK_COL) {
                 if (threadIdx.x == 0) {
                     // bounded wait: a dependency that never completes (a bad task
                     // table) marks the cavity failed and releases its waiters
-                    const unsigned need = (unsigned)d.nrb;
+                    const unsigned need = (unsigned)d.nrb + ctrl[CTRL_EXTRA];
+                    const unsigned limit = ctrl[CTRL_SPIN] ? ctrl[CTRL_SPIN] : (1u << 25);   // ~2 s
                     unsigned spins = 0;
                     // relaxed polls; the acquire fence after the loop pairs
                     // with the row tasks' release increments (an acquire on
@@ -119,20 +122,25 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
                     while (__hip_atomic_load(done + cav, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                         if (__hip_atomic_load(ctrl + CTRL_ABORT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
                         __builtin_amdgcn_s_sleep(2);
-                        if (++spins > (1u << 25)) {   // ~2 s
+                        if (++spins > limit) {
                             (void)__hip_atomic_exchange(ctrl + CTRL_ABORT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            d.counters[CNT_HANG] = 1u;
                             break;
                         }
                     }
+                    // whichever way the wait ended, a cavity whose row pass is
+                    // incomplete is reported failed and its column task skipped
+                    const bool ok = __hip_atomic_load(done + cav, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+                    if (!ok) d.counters[CNT_HANG] = 1u;
+                    s_ok = ok ? 1 : 0;
                 }
                 // one acquire suffices: it invalidates this CU's L1 and this
                 // XCD's L2, which every wave of the workgroup reads through
                 if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __syncthreads();
-                if (blk == 0 && threadIdx.x < 64) finalize_sums(d);
+                run = __builtin_amdgcn_readfirstlane(s_ok) != 0;
+                if (run && blk == 0 && threadIdx.x < 64) finalize_sums(d);
             }
-            (run_if<MODE, ANY, Ss>(d, kind, blk, smem, red) || ...);
+            if (run) (run_if<MODE, ANY, Ss>(d, kind, blk, smem, red) || ...);
             if (kind == TASK_ROW) {
                 // each wave waits for its stores to reach L2; after the
                 // barrier one device-scope release writes the XCD's L2 back

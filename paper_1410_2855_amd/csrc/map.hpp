@@ -254,7 +254,7 @@ __device__ __forceinline__ void finalize_sums(const CavDesc& d) {
 // default kernels carry no code or registers of the others.
 template <class S, typename T, int MODE, int MODEL = 0>
 __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc& d, int y, int lane,
-                                           T* acc) {
+                                           double* acc) {
     constexpr int R = R_FIRST<S>;
     constexpr int B = S::P / R;
     constexpr int P = S::P;
@@ -316,10 +316,14 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
             else eh = ex((T)0.5 * n);
             const T A2 = A[i] * A[i];
             const T aeh = A[i] * eh;
-            acc[0] += I;
-            acc[1] = fma_(A2, I, acc[1]);
-            acc[2] = fma_(aeh * aeh, I, acc[2]);
-            acc[3] += n;
+            // bookkeeping in FP64 from the first term: a product of two
+            // FP32 values is exact in FP64
+            const double Id = (double)I;
+            const double ad = (double)aeh;
+            acc[0] += Id;
+            acc[1] = fma_((double)A2, Id, acc[1]);
+            acc[2] = fma_(ad * ad, Id, acc[2]);
+            acc[3] += (double)n;
             cx<T> g = scale(e, sqR * aeh);
             // phase of the complex aperture: mirror curvature exp(i k r^2/(2F))
             // as the product of its x and y factors, then the roughness
@@ -413,13 +417,12 @@ __device__ __forceinline__ void row_body(const CavDesc& d, int rb, cx<T>* lds, d
         stage_out_rows<S, T, 0>(blk, lds, tid);
         return;
     } else {
-        // per-lane sums in the field's precision (P terms), FP64 from the
-        // wave reduction on
+        // diagnostics sums in FP64 throughout: per lane, across the wave,
+        // across the workgroup
         if constexpr (MODE != ROW_FWD) {
-            T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
             local_step<S, T, MODE, MODEL>(v, nv, d, y, lane, acc);
-            double accd[4] = {(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]};
-            block_sums_store<S>(accd, red, d.partials + 4 * rb, tid);
+            block_sums_store<S>(acc, red, d.partials + 4 * rb, tid);
         }
         fft_line<S, FWD, TWS>(v, myl, lane, tw);
         scatter_out<S, RL>(v, myl, lane);

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -598,6 +599,10 @@ int lsr_sync(lsr_plan p) {
     LSR_HIP(hipMemcpy(c, p->d_counters, sizeof c, hipMemcpyDeviceToHost));
     if (c[CNT_HANG]) {
         LSR_HIP(hipMemset(p->d_counters + CNT_HANG, 0, sizeof(unsigned)));
+        // the skipped column tasks recorded no trace: realign the host's
+        // count with the device's, and the failed call has no trace
+        p->trips_done = c[CNT_TRIPS];
+        p->last_n = 0;
         return set_err(LSR_EDEVICE, "a batched round trip gave up waiting for its row pass (task table error)");
     }
     if (c[CNT_NONFINITE]) {
@@ -617,14 +622,14 @@ int lsr_trace(lsr_plan p, double* out, int capacity) {
     if (n > p->trace_cap) n = p->trace_cap;
     if (n > capacity) n = capacity;
     if (n == 0) return 0;
-    // newest n records of the last call, oldest first
+    // newest n records of the last call, oldest first: one or two contiguous
+    // runs of the ring
     const unsigned long long first = p->trips_done - (unsigned long long)n;
-    std::vector<double> ring(4 * (size_t)p->trace_cap);
-    LSR_HIP(hipMemcpy(ring.data(), p->d_trace, ring.size() * sizeof(double), hipMemcpyDeviceToHost));
-    for (int t = 0; t < n; ++t) {
-        const size_t slot = (size_t)((first + (unsigned long long)t) % (unsigned long long)p->trace_cap);
-        memcpy(out + 4 * (size_t)t, ring.data() + 4 * slot, 4 * sizeof(double));
-    }
+    const size_t slot = (size_t)(first % (unsigned long long)p->trace_cap);
+    const size_t n1 = std::min((size_t)n, (size_t)p->trace_cap - slot);
+    const size_t rec = 4 * sizeof(double);
+    LSR_HIP(hipMemcpy(out, p->d_trace + 4 * slot, n1 * rec, hipMemcpyDeviceToHost));
+    if (n1 < (size_t)n) LSR_HIP(hipMemcpy(out + 4 * n1, p->d_trace, ((size_t)n - n1) * rec, hipMemcpyDeviceToHost));
     return n;
 }
 

@@ -107,6 +107,10 @@ using S512r  = Shape<512, 32, 8, 16, 8, 4>;
 using S1024r = Shape<1024, 64, 4, 16, 16, 4>;
 using S1024t = Shape<1024, 64, 8, 4, 16, 16>;
 using S2048r = Shape<2048, 128, 4, 16, 16, 8>;
+// 4096 with half the lanes per line (32 points per lane, 512 threads): the
+// same 4 x 4 tiles and LDS, two waves per SIMD with the registers to hold
+// every value without spilling.
+using S4096w = Shape<4096, 128, 4, 16, 16, 16>;
 // FP64 complex field (16 B/point): half the lines per workgroup.
 using D256  = Shape<256, 16, 8, 16, 16>;
 using D384  = Shape<384, 16, 8, 8, 12, 4>;
@@ -118,7 +122,8 @@ using D4096 = Shape<4096, 256, 2, 16, 16, 16>;
 
 static_assert(S256::valid() && S384::valid() && S512::valid() && S768::valid() &&
               S1024::valid() && S2048::valid() && S4096::valid(), "bad fp32 shape");
-static_assert(S512r::valid() && S1024r::valid() && S1024t::valid() && S2048r::valid(), "bad alternative shape");
+static_assert(S512r::valid() && S1024r::valid() && S1024t::valid() && S2048r::valid() && S4096w::valid(),
+              "bad alternative shape");
 static_assert(D256::valid() && D384::valid() && D512::valid() && D768::valid() &&
               D1024::valid() && D2048::valid() && D4096::valid(), "bad fp64 shape");
 

@@ -70,6 +70,8 @@ _SIGS = {
     "lsr_batch_roundtrips": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i]),
     "lsr_batch_diag": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(lsr_diag_out)]),
     "lsr_batch_set_graph_trips": (_i, [_vp, _i]),
+    "lsr_batch_prepare": (_i, [_vp, _i]),
+    "lsr_batch_test_wait": (_i, [_vp, _i, _i]),
     "lsr_batch_configure": (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _i, ctypes.POINTER(_i)]),
     "lsr_batch_time_kernels": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i, ctypes.POINTER(_d)]),
     "lsr_batch_destroy": (None, [_vp]),
@@ -276,6 +278,14 @@ def lsr_batch_diag(batch, idx: int, E, Ninv, nbins: int) -> dict:
 
 def lsr_batch_set_graph_trips(batch, k: int):
     _check(load().lsr_batch_set_graph_trips(batch, k))
+
+
+def lsr_batch_prepare(batch, n_trips: int):
+    _check(load().lsr_batch_prepare(batch, n_trips))
+
+
+def lsr_batch_test_wait(batch, extra_need: int, spin_limit: int):
+    _check(load().lsr_batch_test_wait(batch, extra_need, spin_limit))
 
 
 def lsr_batch_configure(batch, engine=-1, variant=-1, wgs_per_cu=-1, chunk=-1, lag=-1, graph_k=-1,

@@ -275,3 +275,91 @@ def test_alternative_fft_plans(N, shape, engine):
     lsr.lsr_batch_destroy(b)
     for p in plans:
         p.close()
+
+
+@pytest.mark.parametrize("engine", [1, 0])
+def test_graphs_for_every_call_length(engine):
+    """Calls of any length replay graphs (whole-call graphs up to k + 1 trips,
+    k-trip graphs plus a remainder graph beyond), prepared or captured on
+    first use, several lengths interleaved so the graph cache is reused and
+    evicted: bitwise the one-cavity path over the same total trips."""
+    cavs = mixed(4, (512, 1024))
+    plans, Es, Ns = make(cavs)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_configure(b, engine=engine, graph_k=4)
+    lengths = [1, 2, 5, 3, 9, 5, 2, 6, 7, 1, 11, 4, 12, 3, 5]   # > 8 distinct graphs over the run
+    lsr.lsr_batch_prepare(b, 5)
+    lsr.lsr_batch_prepare(b, 9)
+    for n in lengths:
+        lsr.lsr_batch_roundtrips(b, Es, Ns, n)
+    for p in plans:
+        p.sync()
+    total = sum(lengths)
+    ref, _ = plain_reference(cavs, total)
+    for i in range(len(cavs)):
+        assert torch.equal(Es[i], ref[i][0]) and torch.equal(Ns[i], ref[i][1]), i
+    # the last call's trace is the last `lengths[-1]` trips of the one-cavity run
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
+
+
+def test_batch_rejects_plans_on_different_streams():
+    cavs = mixed(2, (256,))
+    plans, Es, Ns = make(cavs)
+    other = torch.cuda.Stream()
+    lsr.lsr_plan_set_stream(plans[1].handle, other)
+    with pytest.raises(lsr.LsrError) as ei:
+        lsr.lsr_batch_create([p.handle for p in plans])
+    assert ei.value.code == lsr.LSR_EINVAL
+    lsr.lsr_plan_set_stream(plans[1].handle, torch.cuda.current_stream())
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_roundtrips(b, Es, Ns, 2)
+    # a plan rebound after the batch was built is refused on the next call
+    lsr.lsr_plan_set_stream(plans[0].handle, other)
+    with pytest.raises(lsr.LsrError) as ei:
+        lsr.lsr_batch_roundtrips(b, Es, Ns, 2)
+    assert ei.value.code == lsr.LSR_EINVAL
+    lsr.lsr_plan_set_stream(plans[0].handle, torch.cuda.current_stream())
+    lsr.lsr_batch_roundtrips(b, Es, Ns, 2)
+    torch.cuda.synchronize()
+    ref, _ = plain_reference(cavs, 4)
+    for i in range(len(cavs)):
+        assert torch.equal(Es[i], ref[i][0]) and torch.equal(Ns[i], ref[i][1]), i
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
+
+
+def test_persistent_wait_failure_flags_every_cavity():
+    """The persistent kernel's bounded wait, forced from the host to give up
+    (one row block more than exists, a poll limit of 64): every cavity's
+    column tasks are skipped and flagged, the kernels finish, and every plan
+    reports LSR_EDEVICE once; afterwards the batch runs correctly again."""
+    cavs = mixed(5, (256, 512))
+    plans, Es, Ns = make(cavs)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_configure(b, engine=0, graph_k=0)
+    lsr.lsr_batch_test_wait(b, 1, 64)
+    lsr.lsr_batch_roundtrips(b, Es, Ns, 3)
+    torch.cuda.synchronize()
+    for i, p in enumerate(plans):
+        with pytest.raises(lsr.LsrError) as ei:
+            p.sync()
+        assert ei.value.code == lsr.LSR_EDEVICE, i
+        p.sync()          # the report cleared the flag
+    lsr.lsr_batch_test_wait(b, 0, 0)
+    for c, e, n in zip(cavs, Es, Ns):
+        e0, n0 = initial_state(c)
+        e.copy_(torch.from_numpy(e0).to(e.device, e.dtype))
+        n.copy_(torch.from_numpy(n0).to(n.device, n.dtype))
+    lsr.lsr_batch_roundtrips(b, Es, Ns, 4)
+    for p in plans:
+        p.sync()
+    ref, ref_tr = plain_reference(cavs, 4)
+    for i in range(len(cavs)):
+        assert torch.equal(Es[i], ref[i][0]) and torch.equal(Ns[i], ref[i][1]), i
+        assert np.array_equal(plans[i].trace(4), ref_tr[i]), i
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
