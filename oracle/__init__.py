@@ -69,6 +69,7 @@ class _Params(ctypes.Structure):
         ("model", ctypes.c_int),
         ("slices", ctypes.c_int),
         ("rough", ctypes.POINTER(ctypes.c_double)),
+        ("transfer", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -123,6 +124,8 @@ class CavityParams:
     model: int = 0              # 0 B class (Euler), 1 B class (exact over a trip), 2 class A
     slices: int = 1             # thin gain sheets per iterate (inversion holds one N x N map each)
     rough: np.ndarray | None = None  # N x N roughness phase psi (rad) of Eq. (12), or None
+    transfer: np.ndarray | None = None  # N x N complex transfer function of a general nonlocal step
+                                        # (Eq. (10)), FFT order, row = y frequency; or None
 
     def _c(self):
         p = _Params()
@@ -140,6 +143,9 @@ class CavityParams:
         if self.rough is not None:
             keep.append(np.ascontiguousarray(self.rough, dtype=np.float64).reshape(self.N, self.N))
             p.rough = _dp(keep[-1])
+        if self.transfer is not None:
+            keep.append(np.ascontiguousarray(self.transfer, dtype=np.complex128).reshape(self.N, self.N))
+            p.transfer = _dp(keep[-1].view(np.float64))
         return p, keep
 
 

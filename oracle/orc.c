@@ -229,6 +229,7 @@ static int params_ok(const orc_params* p)
     if (!(p->filter_delta >= 0.0) || !isfinite(p->filter_delta)) return 0;
     if (p->model < 0 || p->model > 2) return 0;
     if (p->slices < 0) return 0;
+    if (p->transfer && (p->filter_delta > 0.0 || p->slices > 1)) return 0;
     return 1;
 }
 
@@ -348,7 +349,12 @@ int orc_run(const orc_params* p, double* E, double* Ninv, int n_trips,
             double fx = signed_index(pp, N) / (N * p->dx);
             double fy = signed_index(q, N) / (N * p->dx);
             size_t i = (size_t)q * N + pp;
-            if (p->filter_delta > 0.0) {
+            if (p->transfer) {
+                /* a general nonlocal step: the convolution of Eq. (10) with
+                 * the caller's kernel, as its transfer function */
+                H[2 * i] = p->transfer[2 * i];
+                H[2 * i + 1] = p->transfer[2 * i + 1];
+            } else if (p->filter_delta > 0.0) {
                 H[2 * i] = exp(-2.0 * M_PI * M_PI * d2 * (fx * fx + fy * fy));
                 H[2 * i + 1] = 0.0;
             } else {

@@ -52,6 +52,17 @@ typedef struct {
     const double* rough;/* N*N phase psi (rad) of the mirror roughness, the
                            random term of the complex aperture of Eq. (12);
                            row-major; NULL = smooth mirror                  */
+    const double* transfer; /* the nonlocal step as a general convolution,
+                           the map with kernel K of Eq. (10):
+                           E_{n+1} = IFFT2(T . FFT2(G)) with T given here as
+                           N*N complex values (interleaved re, im), in FFT
+                           frequency order, row-major (row = y frequency
+                           index q, column = x frequency index p).  For the
+                           kernel of Eq. (10) sampled on the grid,
+                           E_{n+1}(x2) = dx^2 sum_{x1} K(x1 - x2) G(x1),
+                           T(f) = dx^2 sum_u K(u) exp(+2 pi i f.u / N).
+                           NULL = Fresnel propagation (or the filter);
+                           not combined with the filter or several sheets */
 } orc_params;
 
 /* One-dimensional DFT of length n = 2^a 3^b, in place, unnormalized.

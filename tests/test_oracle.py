@@ -751,3 +751,66 @@ def test_random_roughness_is_a_pure_phase_and_adds_to_the_mirror_curvature():
     c, _, _ = oracle.run(passive(n, dx, lam, L, focal=F, rough=psi), e0, np.zeros((n, n)), 2)
     d, _, _ = oracle.run(passive(n, dx, lam, L, rough=psi + lens), e0, np.zeros((n, n)), 2)
     assert rel(c, d) <= 1e-12
+
+
+# ------------------------------------ general nonlocal kernel, Eq. (10) ---
+
+def _kernel_transfer(K, dx):
+    """Transfer function T of the map E_{n+1}(x2) = dx^2 sum_{x1} K(x1 - x2)
+    G(x1) for a kernel sampled at the grid offsets (FFT order):
+    T(f) = dx^2 sum_u K(u) exp(+2 pi i f.u / N), by numpy's inverse FFT."""
+    n = K.shape[0]
+    return dx * dx * n * n * np.fft.ifft2(K)
+
+
+@pytest.mark.parametrize("n", [8, 12])
+def test_general_kernel_map_by_definition(n):
+    """The nonlocal step with a general real kernel K, Eq. (10), against the
+    convolution written out on the grid: E_{n+1}(x2) = dx^2 sum_{x1}
+    K(x1 - x2) G(x1) (periodic), with a kernel that is neither symmetric nor
+    isotropic, so that a reversed or transposed kernel fails; no gain, no
+    aperture, R = 1, so G = E."""
+    dx = 2e-6
+    K = np.random.default_rng(30 + n).standard_normal((n, n))
+    p = passive(n, dx, 1.064e-6, 1e-3)
+    p.transfer = _kernel_transfer(K, dx)
+    e0 = rand_c((n, n), 31 + n)
+    e1, _, _ = oracle.run(p, e0, np.zeros((n, n)), 1)
+    want = np.zeros((n, n), np.complex128)
+    for y2 in range(n):
+        for x2 in range(n):
+            acc = 0j
+            for y1 in range(n):
+                for x1 in range(n):
+                    acc += K[(y1 - y2) % n, (x1 - x2) % n] * e0[y1, x1]
+            want[y2, x2] = dx * dx * acc
+    assert rel(e1, want) <= 1e-13
+
+
+def test_general_kernel_delta_is_a_shift():
+    """K = a single point at offset s = (3, -2) cells with weight 1/dx^2: the
+    step moves the field by exactly -s, E_{n+1}(x) = G(x + s)."""
+    n, dx = 32, 1e-6
+    K = np.zeros((n, n))
+    K[-2 % n, 3] = 1.0 / (dx * dx)
+    p = passive(n, dx, 1.064e-6, 1e-3)
+    p.transfer = _kernel_transfer(K, dx)
+    e0 = rand_c((n, n), 40)
+    e1, _, _ = oracle.run(p, e0, np.zeros((n, n)), 1)
+    assert rel(e1, np.roll(e0, (2, -3), axis=(0, 1))) <= 1e-13
+
+
+def test_general_kernel_with_the_fresnel_transfer_is_the_propagator():
+    """T set to the Fresnel transfer function exp(-i pi lambda L (fx^2+fy^2))
+    reproduces the default nonlocal step (pinned by the Gaussian beam and
+    Talbot imaging above), gain and aperture on."""
+    p = _c1(48)
+    n = p.N
+    f = np.fft.fftfreq(n) / p.dx
+    FX, FY = np.meshgrid(f, f)
+    e0 = rand_c((n, n), 41) * 0.05
+    n0 = np.full((n, n), p.N0)
+    e_ref, n_ref, t_ref = oracle.run(p, e0, n0, 3)
+    p.transfer = np.exp(-1j * np.pi * p.lam * p.L * (FX ** 2 + FY ** 2))
+    e1, n1, t1 = oracle.run(p, e0, n0, 3)
+    assert rel(e1, e_ref) <= 1e-12 and rel(n1, n_ref) <= 1e-14 and rel(t1, t_ref) <= 1e-13

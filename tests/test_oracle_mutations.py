@@ -44,6 +44,12 @@ MUTATIONS = [
      "if (p->model == 2) return exp(0.5 * Nn / (1.0 + I));"),
     ("aperture sum over A instead of A^2", "s2 += a2 * I;",
      "s2 += sqrt(a2) * I;"),
+    ("general kernel conjugated", "H[2 * i + 1] = p->transfer[2 * i + 1];",
+     "H[2 * i + 1] = -p->transfer[2 * i + 1];"),
+    ("general kernel transposed",
+     "H[2 * i] = p->transfer[2 * i];\n                H[2 * i + 1] = p->transfer[2 * i + 1];",
+     "H[2 * i] = p->transfer[2 * ((size_t)pp * N + q)];\n"
+     "                H[2 * i + 1] = p->transfer[2 * ((size_t)pp * N + q) + 1];"),
     ("pump modulation without the N0 factor", "return p->N0 * (1.0 + p->mod_amp * cx * cy);",
      "return p->N0 + p->mod_amp * cx * cy;"),
     ("pump period from (N - 1) dx",
