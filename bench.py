@@ -224,7 +224,79 @@ def summarize_sq(out_dir: str, workload: str, cavities: int, grid: int, workload
     print("\n".join(txt))
 
 
+# L2-to-fabric request counters (at most 4 TCC counters per run), the
+# independent check of the FETCH_SIZE / WRITE_SIZE calibration
+EA_PASSES = {
+    "ea_rd": "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum",
+    "ea_wr": "TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum",
+}
+
+
+def ea_commands(workload_flag: str = ""):
+    return {k: "rocprofv3 --pmc %s --output-format csv -d OUT/%s -o %s -- python3 /root/repo/bench.py %s"
+               "--profile --steps 2 --warmup 1" % (v, k, k, workload_flag) for k, v in EA_PASSES.items()}
+
+
+def summarize_ea(out_dir: str, workload: str, cavities: int, grid: int, workload_flag: str = ""):
+    """profiles/traffic_requests_<cavities>x<grid>.txt: HBM bytes per launch
+    from the request counters by size (read: 32, 64 and 128-byte requests;
+    write: 64-byte requests and the rest as 32-byte), for the passes and for
+    the calibration copy of known size, beside the copy-calibrated
+    FETCH_SIZE / WRITE_SIZE figures of profiles/traffic.json."""
+    import glob as _g
+
+    pts = cavities * grid * grid
+    algo = {"row_pass": ROW_BYTES_PER_PT * pts, "column_pass": COL_BYTES_PER_PT * pts}
+    vals = {}
+    for tag in EA_PASSES:
+        files = _g.glob(os.path.join(out_dir, tag, "*counter_collection.csv"))
+        if not files:
+            continue
+        for r in _read_csv(files[0]):
+            name = r["Kernel_Name"]
+            keys = [k for k, pat in PASS_KERNELS.items() if pat in name and ("Shape<%d," % grid) in name]
+            if COPY_KERNEL in name:
+                keys = ["copy"]
+            for k in keys:
+                vals.setdefault(k, {}).setdefault(r["Counter_Name"].replace("_sum", ""), []).append(
+                    float(r["Counter_Value"]))
+    cmds = ea_commands(workload_flag)
+    txt = ["HBM traffic from the L2-to-fabric request counters: %s" % workload, "",
+           "commands (from /tmp, TMPDIR=/tmp):"] + ["  " + c for c in cmds.values()] + [""]
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            cal = json.load(f)
+    except (OSError, ValueError):
+        cal = {}
+    for k in ("copy", "row_pass", "column_pass"):
+        if k not in vals:
+            continue
+        m = {c: (max(v) if k == "copy" else sum(v) / len(v)) for c, v in vals[k].items()}
+        r32, r64, r128 = m.get("TCC_EA0_RDREQ_32B", 0), m.get("TCC_EA0_RDREQ_64B", 0), m.get("TCC_EA0_RDREQ_128B", 0)
+        rd = 32 * r32 + 64 * r64 + 128 * r128
+        w, w64 = m.get("TCC_EA0_WRREQ", 0), m.get("TCC_EA0_WRREQ_64B", 0)
+        wr = 64 * w64 + 32 * (w - w64)
+        txt.append("%s: read requests %d (32 B %d, 64 B %d, 128 B %d) -> %.1f MiB; write requests %d (64 B %d) "
+                   "-> %.1f MiB" % (k, m.get("TCC_EA0_RDREQ", 0), r32, r64, r128, rd / 2 ** 20, w, w64, wr / 2 ** 20))
+        if k == "copy":
+            txt.append("  the copy moves %.1f MiB each way" % (COPY_BYTES / 2 ** 20))
+        else:
+            txt.append("  requests: %.3f x algorithmic (%d B)" % ((rd + wr) / algo[k], algo[k]))
+            if k in cal:
+                txt.append("  copy-calibrated FETCH_SIZE + WRITE_SIZE (profiles/traffic.json): %.3f x algorithmic"
+                           % (cal[k]["bytes_per_launch"] / algo[k]))
+    txt.append("")
+    txt.append("kernel source hash: " + kernel_source_hash())
+    path = os.path.join(ROOT, "profiles", "traffic_requests_%dx%d.txt" % (cavities, grid))
+    with open(path, "w") as f:
+        f.write("\n".join(txt) + "\n")
+    print("\n".join(txt))
+
+
 WORKLOADS = {
+    "single256": "one cavity at 256^2, F=100, R=0.9, pump 2x, T1=1000, FP64-table form",
+    "single1024": "one cavity at 1024^2, F=300, R=0.95, pump 3x, T1=2000, FP64-table form",
+    "single2048": "one cavity at 2048^2, F=1000, R=0.9, pump 4x, T1=500, FP64-table form",
     "sweep1024": "%d cavities at 1024^2 (sweep parameter draws), FP64-table form",
     "sweep512": "512 cavities, N uniform in {256, 384, 512, 768, 1024} (sweep draws), FP64-table form",
     "structured4096": "16 cavities at 4096^2, F=1000, periodic pump (M = 45..89 periods), FP64-table form",
@@ -236,7 +308,11 @@ ENGINES = {0: "persistent", 1: "grouped", 2: "grouped-pipelined"}
 
 
 def make_workload(name: str, cavities: int):
-    from paper_1410_2855_amd.inputs import structured_4096, sweep, sweep_1024
+    from paper_1410_2855_amd.inputs import plain_256, plain_1024, precision_2048, structured_4096, sweep, sweep_1024
+
+    if name.startswith("single"):
+        return [{"single256": plain_256, "single1024": plain_1024, "single2048": precision_2048}[name]()], \
+            WORKLOADS[name]
 
     if name == "sweep1024":
         return sweep_1024(cavities), WORKLOADS[name] % cavities
@@ -320,6 +396,50 @@ def oracle_per_size(sizes=(256, 384, 512, 768, 1024, 2048, 4096), target_s: floa
     return {"host": host, "per_size": rows}
 
 
+def bench_single(args):
+    """One cavity alone: lsr_roundtrips calls of --steps trips (one launch per
+    pass, no graph), the median of --reps calls; the one-cavity FFT plan from
+    --fft-plan, or the autotuner's choice (-1)."""
+    import torch
+
+    from paper_1410_2855_amd import lsr
+    from paper_1410_2855_amd.inputs import initial_state
+
+    lsr.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    (cav,), workload = make_workload(args.workload, 1)
+    p = lsr.Plan(cav, prec=lsr.LSR_PREC_FP64TAB, stream=torch.cuda.current_stream())
+    if args.fft_plan >= 0:
+        lsr.lsr_plan_set_fft_plan(p.handle, args.fft_plan)
+    else:
+        lsr.lsr_autotune(p.handle, None, TUNE_CACHE)
+    e, n = p.state(*initial_state(cav), device=dev)
+    p.roundtrips(e, n, args.warmup)
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(args.reps):
+        t0 = time.perf_counter()
+        p.roundtrips(e, n, args.steps)
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - t0) / args.steps)
+    t = statistics.median(per)
+    row_ms, col_ms = lsr.lsr_time_kernels(p.handle, e, n, 20)
+    p.sync()
+    p.close()
+    pts = cav.N * cav.N
+    out = {"metric": "grid-pts x round-trips/s, one cavity", "value": pts / t, "unit": "grid-pts*round-trips/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
+           "us_per_trip": t * 1e6, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c64", "data": "synthetic",
+           "config": {"workload": workload, "grid": [cav.N], "cavities": 1, "mode": "one cavity, one launch per pass",
+                      "fft_plan": args.fft_plan if args.fft_plan >= 0 else "autotuned"},
+           "timing": {"reps": len(per), "statistic": "median", "ms_per_step_each": [round(x * 1e3, 5) for x in per]},
+           "kernels_ms": {"row_pass": round(row_ms, 5), "column_pass": round(col_ms, 5)},
+           "hbm_frac_whole_step": round(pts * TRIP_BYTES_PER_PT / t / 1e9 / HBM_PEAK_GBS, 4)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,7 +451,7 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="sweep1024",
                     help="sweep1024 (default, the metric's configuration): 1024^2 cavities with the sweep's "
                          "parameter draws; sweep512: 512 cavities of N in {256..1024}; structured4096: "
-                         "16 cavities at 4096^2 with the periodic pump")
+                         "16 cavities at 4096^2 with the periodic pump; single256/1024/2048: one cavity alone")
     ap.add_argument("--local-step", choices=sorted(LOCAL_STEPS), default="b-euler",
                     help="local step of the map (b-euler: Eq. (1); b-exact: the rate equation solved over "
                          "a trip; class-a: the saturable gain of the class-A laser)")
@@ -342,12 +462,22 @@ def main():
                     help="> 0: every cavity's mirror carries a random roughness phase of this rms (rad), "
                          "4-cell correlation; the row pass then also reads exp(i psi), 8 B per point")
     ap.add_argument("--autotune", action="store_true", help="retune the batch and update the cache")
+    ap.add_argument("--shape", type=int, default=-1,
+                    help=">= 0: run the batch on this FFT plan (0 default, k alternative plan k) instead of "
+                         "the cached one")
+    ap.add_argument("--fft-plan", type=int, default=-1,
+                    help="single-cavity workloads: one-cavity FFT plan (0 default, 1 eight points per lane; "
+                         "-1 the autotuner's choice)")
+    ap.add_argument("--engine", type=int, default=-1,
+                    help=">= 0: run the batch on this engine instead of the cached one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="short batched run for a profiler, plus a copy kernel of known size")
     ap.add_argument("--summarize", metavar="OUT",
                     help="write profiles/ summaries from rocprofv3 csv output under OUT (no GPU)")
+    ap.add_argument("--summarize-ea", metavar="OUT",
+                    help="write profiles/traffic_requests_*.txt from the request-counter runs under OUT (no GPU)")
     ap.add_argument("--summarize-sq", metavar="OUT",
                     help="write profiles/sq_counters_*.txt from the SQ counter runs under OUT (no GPU)")
     ap.add_argument("--oracle-sizes", action="store_true",
@@ -356,6 +486,14 @@ def main():
     args = ap.parse_args()
     if args.oracle_sizes:
         print(json.dumps(oracle_per_size()), flush=True)
+        return
+    if args.summarize_ea:
+        if args.workload == "sweep1024":
+            summarize_ea(args.summarize_ea, WORKLOADS["sweep1024"] % args.cavities, args.cavities, 1024)
+        elif args.workload == "structured4096":
+            summarize_ea(args.summarize_ea, WORKLOADS["structured4096"], 16, 4096, "--workload structured4096 ")
+        else:
+            sys.exit("--summarize-ea covers the single-size workloads (sweep1024, structured4096)")
         return
     if args.summarize_sq:
         if args.workload == "sweep1024":
@@ -379,6 +517,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     os.environ.setdefault("LSR_TUNE_CACHE", TUNE_CACHE)
+    if args.workload.startswith("single"):
+        bench_single(args)
+        return
 
     import numpy as np
     import torch
@@ -420,7 +561,7 @@ def main():
     batch = lsr.lsr_batch_create([p.handle for p in plans])
     if args.autotune:
         lsr.lsr_autotune(None, batch, TUNE_CACHE)
-    cfg = lsr.lsr_batch_configure(batch)
+    cfg = lsr.lsr_batch_configure(batch, engine=args.engine, shape=args.shape)
 
     def run_batched(k):
         lsr.lsr_batch_roundtrips(batch, Es, Ns, k)

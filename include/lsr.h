@@ -163,6 +163,34 @@ int lsr_propagate(lsr_plan p, const void* E_in, double z, void* E_out);
  * their next call.  LSR_EINVAL for delta < 0 or non-finite. */
 int lsr_plan_set_filter(lsr_plan p, double delta);
 
+/* One-cavity FFT plan: k = 0 the size's default shape (the one batches use);
+ * k = 1, for N = 256, 1024 and 2048 in the FP32 forms, a shape with 8 points
+ * per lane and more lanes per line (256: 32 lanes x 8 lines, radices 8 8 4;
+ * 1024: 128 lanes x 4 lines, 8 8 4 4; 2048: 256 lanes x 4 lines, 8 8 8 4),
+ * whose shorter per-lane instruction chain suits a lone cavity, which keeps
+ * at most one workgroup per CU busy.  Every plan computes the same transform
+ * (results differ only by FP32 rounding); the twiddle table is rebuilt in
+ * FP64 for the shape.  lsr_autotune(p, NULL, path) times the plans of the
+ * size and keeps the fastest.  Waits for the plan's stream.  LSR_EUNSUPPORTED
+ * where plan k is not compiled. */
+int lsr_plan_set_fft_plan(lsr_plan p, int k);
+
+/* General nonlocal step: the map with a kernel K of Eq. (10),
+ * E_{n+1}(x2) = integral K(x1 - x2) G(x1) dx1 (Sec. 2.2; the real kernel of
+ * the confocal 8F cavity, or any other convolution), given by its transfer
+ * function: E_{n+1} = IFFT2(T . FFT2(G)).  T: HOST array of N*N complex
+ * values (2*N*N doubles, interleaved re, im), frequency order, row-major
+ * (row = y frequency index q, column = x frequency index p; index q*N + p);
+ * read during the call only.  For a kernel sampled at the grid offsets u,
+ * T(f) = dx^2 sum_u K(u) exp(+2 pi i f.u/N).  NULL restores the propagator
+ * (or the filter of lsr_plan_set_filter).  The plan keeps T/N^2 by column in
+ * its precision (8 B per point, 16 for FP64 plans), read by the column pass
+ * in every precision form: the column pass then moves 8 (16) more bytes per
+ * point.  One gain sheet only (LSR_EINVAL with several); batches refuse such
+ * plans (LSR_EUNSUPPORTED).  Waits for the plan's stream and allocates the
+ * table (the previous one is freed).  LSR_EINVAL for a non-finite value. */
+int lsr_plan_set_transfer(lsr_plan p, const double* T);
+
 /* Several thin gain sheets per round trip: the active medium spread along
  * the cavity instead of concentrated at one plane (the distributed-gain
  * variant the paper notes in Sec. 2.2 after Eq. (12)).  With m > 1 sheets a
@@ -178,8 +206,11 @@ int lsr_plan_set_filter(lsr_plan p, double delta);
  * values, sheet k at element offset k*N*N; lsr_diag reads sheet 0; the trace
  * holds sheet 0's sums.  Launches: 2m per trip plus 1.  Waits for the plan's
  * stream and allocates the table of the step (the previous one is freed).
- * Batches run single-sheet plans only: lsr_batch_create and
- * lsr_batch_roundtrips return LSR_EUNSUPPORTED for m > 1.
+ * Batches run plans of several sheets when every plan of the batch has the
+ * same m (each sheet step is one grouped row pass and one grouped column
+ * pass over all cavities, or one persistent launch); lsr_batch_create and
+ * lsr_batch_roundtrips return LSR_EUNSUPPORTED when the counts differ, and
+ * lsr_batch_time_kernels for m > 1.
  * LSR_EINVAL unless 1 <= m <= LSR_MAX_SLICES. */
 #define LSR_MAX_SLICES 64
 int lsr_plan_set_slices(lsr_plan p, int m);
@@ -257,8 +288,8 @@ void lsr_plan_destroy(lsr_plan p);
 /* ---------------------------------------------------------------------- */
 /* Batching: many cavities of uneven N and parameters advanced together,  */
 /* by one grouped launch per pass or one persistent kernel per round trip, */
-/* replayed as a HIP graph of k round trips.  Batches take                 */
-/* LSR_PREC_FP64TAB plans of one gain sheet, any local-step model.         */
+/* replayed as HIP graphs.  Batches take LSR_PREC_FP64TAB plans, any       */
+/* local-step model, roughness and filter, and one number of gain sheets.  */
 /* ---------------------------------------------------------------------- */
 
 /* Build a batch over count >= 1 plans (borrowed).  The launch
@@ -350,8 +381,11 @@ void lsr_batch_destroy(lsr_batch b);
  * and residency, graph length) on the device with scratch state, keep the
  * fastest, and store it in the JSON cache at cache_path (NULL =
  * $LSR_TUNE_CACHE or no file).  The winner applies to the batch at once and
- * to later batches of the same sizes.  A plan alone (b = NULL) has a single
- * compiled plan per size and nothing to choose.  Synchronises. */
+ * to later batches of the same sizes.  A plan alone (b = NULL): the cached
+ * one-cavity FFT plan of its size and precision form if the cache holds one,
+ * else the fastest of its compiled one-cavity FFT plans, timed on scratch
+ * state and stored; applied to the plan (lsr_plan_set_fft_plan).
+ * Synchronises. */
 int lsr_autotune(lsr_plan p, lsr_batch b, const char* cache_path);
 
 /* ---------------------------------------------------------------------- */
@@ -360,6 +394,12 @@ int lsr_autotune(lsr_plan p, lsr_batch b, const char* cache_path);
 
 const char* lsr_last_error(void);
 const char* lsr_version(void);
+
+/* Failure-path hook for tests: the device allocation made after `after`
+ * more successful ones (0 = the next one) fails as if the device were out of
+ * memory, once; -1 switches the hook off.  Every entry point that allocates
+ * then returns LSR_ENOMEM and frees what it had allocated in that call. */
+int lsr_test_fail_alloc(int after);
 
 /* Whether grid size N is compiled in for prec (1) or not (0). */
 int lsr_supported(int N, int prec);

@@ -209,7 +209,7 @@ struct BatchGroup {
     int4* d_cols = nullptr;          // column tasks only (grouped column pass)
     int ncols = 0;
     unsigned* d_ctrl = nullptr;
-    void* d_tw = nullptr;            // twiddles of an alternative plan (else the plans' own)
+    void* d_tw[8] = {};              // twiddles of each size of the group, for its FFT plan
     int occ[4] = {1, 1, 1, 1};   // resident workgroups per CU of each variant
     int occ_pipe[4][2] = {};     // same for the pipelined row / column pass
 };
@@ -225,6 +225,7 @@ struct lsr_batch_s {
     std::vector<void*> lastE, lastN;
     std::vector<unsigned> lastVer;   // plan descriptor versions of the last upload
     std::vector<int> models;         // the plans' local-step codes (model, roughness) when grouped
+    int sheets = 1;                  // gain sheets per round trip, the same for every plan
     Tune tune;
     std::string key;
     // captured launch sequences, reused across calls (see run_trips)
@@ -246,7 +247,8 @@ static void groups_free(lsr_batch_s* b) {
         if (g.d_last) (void)hipFree(g.d_last);
         if (g.d_cols) (void)hipFree(g.d_cols);
         if (g.d_ctrl) (void)hipFree(g.d_ctrl);
-        if (g.d_tw) (void)hipFree(g.d_tw);
+        for (void* t : g.d_tw)
+            if (t) (void)hipFree(t);
     }
     b->grp.clear();
     b->lastE.clear();
@@ -293,9 +295,9 @@ static int batch_pack(lsr_batch_s* b) {
         if (g.d_last) (void)hipFree(g.d_last);
         if (g.d_cols) (void)hipFree(g.d_cols);
         g.d_tasks = g.d_last = g.d_cols = nullptr;
-        if (hipMalloc(&g.d_tasks, t.size() * sizeof(int4)) != hipSuccess ||
-            hipMalloc(&g.d_last, l.size() * sizeof(int4)) != hipSuccess ||
-            hipMalloc(&g.d_cols, cols.size() * sizeof(int4)) != hipSuccess)
+        if (dev_malloc((void**)&g.d_tasks, t.size() * sizeof(int4)) != hipSuccess ||
+            dev_malloc((void**)&g.d_last, l.size() * sizeof(int4)) != hipSuccess ||
+            dev_malloc((void**)&g.d_cols, cols.size() * sizeof(int4)) != hipSuccess)
             return set_err(LSR_ENOMEM, "task table allocation failed");
         LSR_HIP(hipMemcpy(g.d_tasks, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice));
         LSR_HIP(hipMemcpy(g.d_last, l.data(), l.size() * sizeof(int4), hipMemcpyHostToDevice));
@@ -316,6 +318,7 @@ static int batch_pack(lsr_batch_s* b) {
 // alternative plan) and packs their task lists.
 static int batch_partition(lsr_batch_s* b) {
     groups_free(b);
+    b->sheets = b->plans[0]->slices;
     // sizes with a cavity of another local-step code than the default run on
     // kernels for that size alone (key -(64N + level)): level ANY_FIXED + m
     // when every cavity of the size has model m and a smooth mirror, else 1
@@ -375,16 +378,17 @@ static int batch_partition(lsr_batch_s* b) {
         const size_t ncav = bg.cav.size();
         b->grp.push_back(bg);
         BatchGroup& g = b->grp.back();
-        if (hipMalloc(&g.d_desc, ncav * sizeof(CavDesc)) != hipSuccess ||
-            hipMalloc(&g.d_ctrl, (CTRL_ROWDONE + ncav) * sizeof(unsigned)) != hipSuccess)
+        if (dev_malloc((void**)&g.d_desc, (size_t)b->sheets * ncav * sizeof(CavDesc)) != hipSuccess ||
+            dev_malloc((void**)&g.d_ctrl, (CTRL_ROWDONE + ncav) * sizeof(unsigned)) != hipSuccess)
             return set_err(LSR_ENOMEM, "batch allocation failed");
-        if (best->alt != 0) {
-            // twiddles of the alternative plan, FP64-built like a plan's own
-            const std::vector<double> tw = build_twiddles(best->shapes[0], false, true);
+        // the twiddles of each size under the group's FFT plan, FP64-built
+        // like a plan's own (a plan's table may be of another shape)
+        for (int k = 0; k < best->nsizes; ++k) {
+            const std::vector<double> tw = build_twiddles(best->shapes[k], false, true);
             std::vector<float> twf(tw.begin(), tw.end());
-            if (hipMalloc(&g.d_tw, twf.size() * sizeof(float)) != hipSuccess)
+            if (dev_malloc(&g.d_tw[k], twf.size() * sizeof(float)) != hipSuccess)
                 return set_err(LSR_ENOMEM, "batch allocation failed");
-            LSR_HIP(hipMemcpy(g.d_tw, twf.data(), twf.size() * sizeof(float), hipMemcpyHostToDevice));
+            LSR_HIP(hipMemcpy(g.d_tw[k], twf.data(), twf.size() * sizeof(float), hipMemcpyHostToDevice));
         }
         std::vector<unsigned> ctrl(CTRL_ROWDONE + ncav, 0u);
         ctrl[CTRL_NCAV] = (unsigned)ncav;
@@ -406,10 +410,14 @@ static int grid_of(const lsr_batch_s* b, const BatchGroup& g) {
 }
 
 // One grouped pass (kind TASK_ROW or TASK_COL) of every group.
-static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind, LaunchEvents ev = {}) {
+// Descriptors of gain sheet k of group g (the group's cavities, sheet-major).
+static const CavDesc* sheet_descs(const BatchGroup& g, int k) { return g.d_desc + (size_t)k * g.cav.size(); }
+
+static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind, LaunchEvents ev = {}, int sheet = 0) {
     const size_t ng = b->grp.size();
     for (size_t i = 0; i < ng; ++i) {
         auto& g = b->grp[i];
+        const CavDesc* descs = sheet_descs(g, sheet);
         const int v = variant_of(b, g);
         const KernelVariant& kv = g.g->var[v];
         const int4* tasks = kind == TASK_ROW ? g.d_last : g.d_cols;
@@ -420,9 +428,9 @@ static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind, LaunchEvents 
         if (i + 1 == ng) e.stop = ev.stop;
         int rc;
         if (b->tune.engine == 2 && kv.launch_pipe)
-            rc = kv.launch_pipe(mode, kind, b->stream, g.d_desc, tasks, nt, g.occ_pipe[v][kind] * b->cus, e);
+            rc = kv.launch_pipe(mode, kind, b->stream, descs, tasks, nt, g.occ_pipe[v][kind] * b->cus, e);
         else
-            rc = kv.launch_pass(mode, kind, b->stream, g.d_desc, tasks, nt, e);
+            rc = kv.launch_pass(mode, kind, b->stream, descs, tasks, nt, e);
         if (rc)
             return set_err(LSR_EDEVICE, "%s-pass launch failed: %s", kind == TASK_ROW ? "row" : "column",
                            hipGetErrorString(hipGetLastError()));
@@ -430,27 +438,36 @@ static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind, LaunchEvents 
     return LSR_OK;
 }
 
+// One round trip of every cavity (mode ROW_FIRST or ROW_MID), or the last
+// row pass of a call (ROW_LAST).  With m gain sheets a trip is m steps: the
+// row pass of sheet k (sheet 0 in `mode`, the others as middle passes), then
+// its column pass; the column pass of sheet 0 folds the trip's sums.
 static int launch_trip(lsr_batch_s* b, int mode, LaunchEvents ev) {
-    if (b->tune.engine >= 1) {
-        // grouped: every cavity's row blocks, then every cavity's column blocks
-        int rc = launch_grouped_pass(b, mode, TASK_ROW);
-        if (rc == LSR_OK && mode != ROW_LAST) rc = launch_grouped_pass(b, mode, TASK_COL);
-        return rc;
+    const int m = mode == ROW_LAST ? 1 : b->sheets;
+    int rc = LSR_OK;
+    for (int k = 0; k < m && rc == LSR_OK; ++k) {
+        const int md = k == 0 ? mode : ROW_MID;
+        if (b->tune.engine >= 1) {
+            // grouped: every cavity's row blocks, then every cavity's column blocks
+            rc = launch_grouped_pass(b, md, TASK_ROW, {}, k);
+            if (rc == LSR_OK && md != ROW_LAST) rc = launch_grouped_pass(b, md, TASK_COL, {}, k);
+            continue;
+        }
+        const size_t ng = b->grp.size();
+        for (size_t i = 0; i < ng && rc == LSR_OK; ++i) {
+            auto& g = b->grp[i];
+            const bool last = md == ROW_LAST;
+            const int nt = last ? g.nlast : g.ntasks;
+            const int grid = std::min(grid_of(b, g), nt);
+            LaunchEvents e;
+            if (i == 0 && k == 0) e.start = ev.start;
+            if (i + 1 == ng && k + 1 == m) e.stop = ev.stop;
+            if (g.g->var[variant_of(b, g)].launch(md, grid, b->stream, sheet_descs(g, k), last ? g.d_last : g.d_tasks,
+                                                  nt, g.d_ctrl, last ? 1 : b->tune.chunk, e))
+                rc = set_err(LSR_EDEVICE, "persistent kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+        }
     }
-    const size_t ng = b->grp.size();
-    for (size_t i = 0; i < ng; ++i) {
-        auto& g = b->grp[i];
-        const bool last = mode == ROW_LAST;
-        const int nt = last ? g.nlast : g.ntasks;
-        const int grid = std::min(grid_of(b, g), nt);
-        LaunchEvents e;
-        if (i == 0) e.start = ev.start;
-        if (i + 1 == ng) e.stop = ev.stop;
-        if (g.g->var[variant_of(b, g)].launch(mode, grid, b->stream, g.d_desc, last ? g.d_last : g.d_tasks, nt,
-                                              g.d_ctrl, last ? 1 : b->tune.chunk, e))
-            return set_err(LSR_EDEVICE, "persistent kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
-    }
-    return LSR_OK;
+    return rc;
 }
 
 // Graph kinds: GRAPH_MID holds `len` middle round trips (tiled state in and
@@ -536,8 +553,11 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
     if (same) return LSR_OK;
     for (auto& g : b->grp) {
         std::vector<CavDesc> h;
+        for (int k = 0; k < b->sheets; ++k)
         for (int c : g.cav) {
-            CavDesc d = b->plans[c]->d;
+            CavDesc d = plan_sheet_desc(b->plans[c], E[c], N[c], k);
+            // only sheet 0's column pass folds the trip's sums into the trace
+            if (k > 0) d.trace = nullptr;
             // the roughness kernels read d.rough without a check; a group runs
             // only the local-step codes it was compiled for
             if (((d.model & MODEL_ROUGH) != 0) != (d.rough != nullptr))
@@ -546,9 +566,8 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
             const bool runs = lvl >= ANY_FIXED ? d.model == lvl - ANY_FIXED
                             : lvl == 2 ? true : lvl == 1 ? (d.model & MODEL_ROUGH) == 0 : d.model == 0;
             if (!runs) return set_err(LSR_EINVAL, "cavity %d: local-step code %d not in its group", c, d.model);
-            d.E = E[c];
-            d.Ninv = N[c];
-            if (g.d_tw) d.tw = g.d_tw;
+            for (int k = 0; k < g.g->nsizes; ++k)
+                if (g.g->sizes[k] == d.N) d.tw = g.d_tw[k];
             d.nrb = group_blocks(g, d.N);
             h.push_back(d);
         }
@@ -565,7 +584,7 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
 // A plan's local-step code (model, roughness) changed since the batch was
 // grouped: regroup (the kernels of a group read the codes it was built for).
 static int regroup_if_models_changed(lsr_batch_s* b) {
-    bool same = b->models.size() == b->plans.size();
+    bool same = b->models.size() == b->plans.size() && b->sheets == b->plans[0]->slices;
     for (size_t i = 0; same && i < b->plans.size(); ++i) same = b->models[i] == b->plans[i]->d.model;
     if (same) return LSR_OK;
     LSR_HIP(hipStreamSynchronize(b->stream));
@@ -647,8 +666,10 @@ int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count) {
         if (plans[i]->prec != PREC_FP64TAB)
             return set_err(LSR_EUNSUPPORTED, "only FP64TAB plans (FP32 field, FP64-built tables) can be batched");
         if (plans[i]->device != plans[0]->device) return set_err(LSR_EINVAL, "plans on different devices");
-        if (plans[i]->slices != 1)
-            return set_err(LSR_EUNSUPPORTED, "plan %d: batches run single-sheet plans only", i);
+        if (plans[i]->slices != plans[0]->slices)
+            return set_err(LSR_EUNSUPPORTED, "plan %d: every plan of a batch must have the same number of gain sheets", i);
+        if (plans[i]->d_trans)
+            return set_err(LSR_EUNSUPPORTED, "plan %d: batches run the propagator or the filter, not a general transfer function", i);
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return set_err(LSR_EINVAL, "plan %d appears twice", i);
         if (plans[i]->stream != plans[0]->stream)
@@ -754,8 +775,10 @@ int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* N, int n_trip
     for (size_t i = 0; i < b->plans.size(); ++i) {
         if (!E[i] || !N[i] || ((uintptr_t)E[i] & 15u) || ((uintptr_t)N[i] & 15u))
             return set_err(LSR_EINVAL, "state %zu: NULL or not 16-byte aligned", i);
-        if (b->plans[i]->slices != 1)
-            return set_err(LSR_EUNSUPPORTED, "plan %zu: batches run single-sheet plans only", i);
+        if (b->plans[i]->slices != b->plans[0]->slices)
+            return set_err(LSR_EUNSUPPORTED, "plan %zu: every plan of a batch must have the same number of gain sheets", i);
+        if (b->plans[i]->d_trans)
+            return set_err(LSR_EUNSUPPORTED, "plan %zu: batches run the propagator or the filter, not a general transfer function", i);
     }
     if (check_streams(b)) return LSR_EINVAL;
     if (n_trips == 0) return LSR_OK;
@@ -780,6 +803,7 @@ int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* N, int n_tr
     if (!b || !ms || !E || !N) return set_err(LSR_EINVAL, "bad arguments");
     if (n_trips < 1) return set_err(LSR_EINVAL, "n_trips < 1");
     if (check_streams(b)) return LSR_EINVAL;
+    if (b->plans[0]->slices != 1) return set_err(LSR_EUNSUPPORTED, "kernel timing covers single-sheet batches");
     DeviceGuard dg(b->device);
     LSR_HIP(hipEventRecord(b->ev_in, b->user));
     LSR_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
@@ -868,12 +892,68 @@ static double time_batch(lsr_batch_s* b, const std::vector<void*>& E, const std:
     return rc == 0 ? ms / trips : -1;
 }
 
+// One-cavity FFT plan of a plan alone: the cached choice for its size and
+// precision form, else the fastest compiled one, timed over 200 trips on
+// zero scratch state (the kernels have no data-dependent paths) and stored.
+static int tune_plan(lsr_plan p, const char* path) {
+    const std::string key = "gfx950:plan:" + std::to_string(p->N) + ":" + std::to_string(p->prec);
+    const std::string cp = cache_path(path);
+    auto cache = cache_read(cp);
+    auto it = cache.find(key);
+    if (it != cache.end()) return lsr_plan_set_fft_plan(p, it->second.shape);
+    std::vector<int> cands = {0};
+    for (int k = 1; k <= 1; ++k)
+        if (p->prec != PREC_FP64 && launchers_alt(p->N, k)) cands.push_back(k);
+    DeviceGuard dg(p->device);
+    LSR_HIP(hipStreamSynchronize(p->stream));
+    const size_t pts = (size_t)p->N * p->N;
+    void *E = nullptr, *Nv = nullptr;
+    if (dev_malloc(&E, pts * 2 * p->real_bytes()) != hipSuccess ||
+        dev_malloc(&Nv, pts * p->real_bytes() * (size_t)p->slices) != hipSuccess) {
+        if (E) (void)hipFree(E);
+        return set_err(LSR_ENOMEM, "autotune scratch allocation failed");
+    }
+    (void)hipMemset(E, 0, pts * 2 * p->real_bytes());
+    (void)hipMemset(Nv, 0, pts * p->real_bytes() * (size_t)p->slices);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    int best = -1, rc = LSR_OK;
+    float best_ms = 1e30f;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) rc = set_err(LSR_EDEVICE, "hipEventCreate failed");
+    for (int k : cands) {
+        if (rc != LSR_OK) break;
+        if ((rc = lsr_plan_set_fft_plan(p, k)) != LSR_OK) break;
+        if ((rc = lsr_roundtrips(p, E, Nv, 20)) != LSR_OK) break;   // warm-up
+        (void)hipEventRecord(t0, p->stream);
+        if ((rc = lsr_roundtrips(p, E, Nv, 200)) != LSR_OK) break;
+        (void)hipEventRecord(t1, p->stream);
+        float ms = 0;
+        if (hipEventSynchronize(t1) != hipSuccess || hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+            rc = set_err(LSR_EDEVICE, "autotune timing failed");
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = k;
+        }
+    }
+    (void)hipStreamSynchronize(p->stream);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    (void)hipFree(E);
+    (void)hipFree(Nv);
+    if (rc != LSR_OK) return rc;
+    rc = lsr_plan_set_fft_plan(p, best);
+    if (rc != LSR_OK || cp.empty()) return rc;
+    Tune t;
+    t.shape = best;
+    cache[key] = t;
+    if (!cache_write(cp, cache)) return set_err(LSR_EINVAL, "cannot write tune cache %s", cp.c_str());
+    return LSR_OK;
+}
+
 int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
     if (!p && !b) return set_err(LSR_EINVAL, "nothing to tune");
-    if (p && !b) {
-        // one-cavity plans have one compiled shape per size: nothing to choose
-        return LSR_OK;
-    }
+    if (p && !b) return tune_plan(p, path);
     DeviceGuard dg(b->device);
     LSR_HIP(hipStreamSynchronize(b->user));
     // scratch state: zero fields (the kernels have no data-dependent paths)
@@ -885,7 +965,7 @@ int lsr_autotune(lsr_plan p, lsr_batch b, const char* path) {
     for (auto* q : b->plans) {
         void *e = nullptr, *n = nullptr;
         const size_t pts = (size_t)q->N * q->N;
-        if (hipMalloc(&e, pts * 8) != hipSuccess || hipMalloc(&n, pts * 4) != hipSuccess) {
+        if (dev_malloc(&e, pts * 8) != hipSuccess || dev_malloc(&n, pts * 4) != hipSuccess) {
             if (e) (void)hipFree(e);
             release();
             return set_err(LSR_ENOMEM, "autotune scratch allocation failed");

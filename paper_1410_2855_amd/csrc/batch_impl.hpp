@@ -138,7 +138,8 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
                 if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __syncthreads();
                 run = __builtin_amdgcn_readfirstlane(s_ok) != 0;
-                if (run && blk == 0 && threadIdx.x < 64) finalize_sums(d);
+                // the trip's sums, folded once per trip (sheet 0 only)
+                if (run && blk == 0 && threadIdx.x < 64 && d.trace) finalize_sums(d);
             }
             if (run) (run_if<MODE, ANY, Ss>(d, kind, blk, smem, red) || ...);
             if (kind == TASK_ROW) {
@@ -204,7 +205,9 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
     const int blk = __builtin_amdgcn_readfirstlane(tk.z);
     const CavDesc& d = descs[cav];
     if constexpr (KIND == TASK_COL) {
-        if (blk == 0 && threadIdx.x < 64) finalize_sums(d);
+        // the trip's sums, folded once per trip (the descriptors of the other
+        // gain sheets carry no trace)
+        if (blk == 0 && threadIdx.x < 64 && d.trace) finalize_sums(d);
     }
     if constexpr (HXLDS) (col_task_hx_lds<Ss>(d, blk, smem), ...);
     else (run_if<MODE, ANY, Ss>(d, KIND, blk, smem, red) || ...);
@@ -262,7 +265,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
             const int cavn = more ? __builtin_amdgcn_readfirstlane(tasks[tn].x) : 0;
             const int blkn = more ? __builtin_amdgcn_readfirstlane(tasks[tn].z) : 0;
             const CavDesc& d = descs[cav];
-            if (blk == 0 && threadIdx.x < 64) finalize_sums(d);
+            if (blk == 0 && threadIdx.x < 64 && d.trace) finalize_sums(d);
             col_body<S, float, COL_PROP, PROP_TABLE, TW_LDS, true>(d, blk, lds, in, [&] {
                 if (more) col_load<S, float, COL_PROP, true>(descs[cavn], blkn, in);
             }, ltw, lhx);

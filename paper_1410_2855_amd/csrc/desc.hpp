@@ -38,10 +38,14 @@ struct CavDesc {
     const void* foc;        // exp(i pi x_i^2/(lambda F)), N complex entries, or null (flat mirror)
     const void* mask;       // N*N aperture amplitude (AP_MASK) or null
     const void* rough;      // N*N exp(i psi) of the mirror roughness psi, complex, or null
+    const void* trans;      // N*N complex transfer function of a general nonlocal step
+                            // (prop_kind 2), stored by column: frequency (p, q) at p*N + q,
+                            // 1/N^2 folded in; or null
     void* scratch;          // DIAG: tiled forward row transform of G (N*N complex)
     double* partials;       // per row block: 4 sums
     double* radial_part;    // DIAG: per column block radial spectrum partials
-    double* trace;          // ring of trace_cap records of 4 sums
+    double* trace;          // ring of trace_cap records of 4 sums; null in the batch descriptors
+                            // of gain sheets other than 0 (their column pass folds no sums)
     unsigned* counters;     // CNT_WORDS words
     int N;
     int prec;
@@ -50,7 +54,8 @@ struct CavDesc {
     int trace_cap;
     int nrb;                // row blocks = column blocks = N / LPW
     int nbins;
-    int prop_kind;          // 0 Fresnel propagator (hx), 1 real filter table (hx holds it)
+    int prop_kind;          // 0 Fresnel propagator (hx), 1 real filter table (hx holds it),
+                            // 2 general transfer function (trans)
     int model;              // local-step code: bits 0-1 the model, 0 B class (Euler
                             // update), 1 B class (exact update over a trip), 2 class A
                             // (saturable gain); MODEL_ROUGH set exactly when rough is

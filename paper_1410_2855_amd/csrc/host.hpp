@@ -14,6 +14,10 @@ namespace lsr {
 
 int set_err(int code, const char* fmt, ...);
 
+// hipMalloc for every device allocation of the library, so that a test can
+// force a failure from the host (lsr_test_fail_alloc).
+hipError_t dev_malloc(void** p, size_t bytes);
+
 #define LSR_HIP(call)                                                                     \
     do {                                                                                  \
         hipError_t e_ = (call);                                                           \
@@ -56,6 +60,7 @@ struct lsr_plan_s {
     double filter = 0;                 // > 0: width of the real filter replacing the propagator
     int model = 0;                     // lsr_model
     int slices = 1;                    // thin gain sheets per round trip
+    int fft_plan = 0;                  // one-cavity FFT plan (0 default shape, 1 eight points per lane)
     unsigned version = 0;              // bumped whenever the descriptor d changes
     hipStream_t stream = nullptr;
     const lsr::Launchers* kern = nullptr;
@@ -69,6 +74,7 @@ struct lsr_plan_s {
     void* d_hz = nullptr;            // propagator table of the last lsr_propagate distance
     void* d_hs = nullptr;            // nonlocal step between two of several gain sheets
     void* d_rough = nullptr;         // exp(i psi) of the mirror roughness, N*N complex, or null
+    void* d_trans = nullptr;         // general transfer function, N*N complex by column, or null
     double* d_partials = nullptr;
     double* d_trace = nullptr;
     unsigned* d_counters = nullptr;
@@ -80,3 +86,10 @@ struct lsr_plan_s {
     int last_n = 0;
     size_t real_bytes() const { return prec == lsr::PREC_FP64 ? 8 : 4; }
 };
+
+namespace lsr {
+// Descriptor of gain sheet k (of the plan's m) for a call on (E, Ninv): the
+// sheet's inversion, pump N0/m and step table; the mirror, aperture and
+// roughness on sheet 0 only (plan.hip).
+CavDesc plan_sheet_desc(const lsr_plan_s* p, void* E, void* Ninv, int k);
+}  // namespace lsr

@@ -60,9 +60,16 @@ int launch_col_t(const CavDesc& d, int mode, hipStream_t st) {
     switch (mode) {
     case COL_PROP:
         // the plain form evaluates the Fresnel phase on the device; a filter
-        // (or any FP64-built propagator) comes from the table
-        if (d.prec == PREC_PLAIN && d.prop_kind == 0) hipLaunchKernelGGL((k_col<S, T, COL_PROP, PROP_PHASE>), g, b, 0, st, d);
-        else hipLaunchKernelGGL((k_col<S, T, COL_PROP, PROP_TABLE>), g, b, 0, st, d);
+        // (or any FP64-built propagator) comes from the table; a general
+        // transfer function from its own N x N table
+        if (d.prop_kind == 2) {
+            if (!d.trans) return -1;
+            hipLaunchKernelGGL((k_col<S, T, COL_PROP, PROP_TRANS>), g, b, 0, st, d);
+        } else if (d.prec == PREC_PLAIN && d.prop_kind == 0) {
+            hipLaunchKernelGGL((k_col<S, T, COL_PROP, PROP_PHASE>), g, b, 0, st, d);
+        } else {
+            hipLaunchKernelGGL((k_col<S, T, COL_PROP, PROP_TABLE>), g, b, 0, st, d);
+        }
         break;
     case COL_DIAG: hipLaunchKernelGGL((k_col<S, T, COL_DIAG, PROP_TABLE>), g, b, 0, st, d); break;
     case COL_FREE:

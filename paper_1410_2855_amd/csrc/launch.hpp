@@ -17,6 +17,10 @@ struct Launchers {
 // nullptr if grid size N is not compiled in for the precision class.
 const Launchers* launchers_for(int N, bool fp64);
 
+// One-cavity FFT plan k > 0 of the FP32 forms for size N (k = 1: 8 points
+// per lane), or nullptr where none is compiled.
+const Launchers* launchers_alt(int N, int k);
+
 // Shape of N without touching HIP (table builders, introspection).
 bool shape_for(int N, bool fp64, ShapeInfo* out);
 

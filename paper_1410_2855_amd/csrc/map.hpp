@@ -246,8 +246,9 @@ __device__ __forceinline__ void finalize_sums(const CavDesc& d) {
 
 // ---------------------------------------------------------------------------
 // Local step, inversion update and diagnostics sums on the lane's points of
-// row y (register order of the first forward radix = natural x order).  Done
-// in phases over all P points so the aperture power runs as one uniform loop.
+// row y (register order of the first forward radix = natural x order), in
+// chunks of four points: the aperture power of a chunk runs as one loop
+// uniform across lanes.
 // MODEL is the local-step code: its low bits select the local step (0 B class
 // with the Euler update, 1 B class with the update exact over a trip, 2 class
 // A), MODEL_ROUGH adds the roughness factor.  A compile-time choice, so the
@@ -273,38 +274,45 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
     // byte offsets of row y from the cavity's (uniform) array bases
     const unsigned row = (unsigned)y * (unsigned)S::N * (unsigned)sizeof(T);
 
-    // aperture amplitude A(x, y)
-    T A[P];
-    if (kind == AP_MASK) {
-        sfor<0, P>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            A[i] = gld<T>(d.mask, row + (unsigned)sizeof(T) * (unsigned)reg_pos<S, R>(lane, i / R, i % R));
-        });
-    } else if (kind == AP_NONE) {
-        sfor<0, P>([&](auto ic) { A[decltype(ic)::value] = (T)1; });
-    } else {
-        // u = r^2/r0^2 (super-Gaussian) or r^2/(2 r0^2) (Gaussian); exponent
-        // u^h, h = order/2, by squaring (uniform loop)
-        T u[P];
-        sfor<0, P>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            const T X = ((T)reg_pos<S, R>(lane, i / R, i % R) - half) * dx;
-            u[i] = fma_(X, X, Y2) * ir;
-            A[i] = (T)1;
-        });
-        for (int e = kind == AP_SUPERGAUSS ? d.ap_half_order : 1; e; e >>= 1) {
-            if (e & 1) sfor<0, P>([&](auto ic) { A[decltype(ic)::value] *= u[decltype(ic)::value]; });
-            sfor<0, P>([&](auto ic) { u[decltype(ic)::value] *= u[decltype(ic)::value]; });
-        }
-        sfor<0, P>([&](auto ic) { A[decltype(ic)::value] = ex(-A[decltype(ic)::value]); });
-    }
     const T pcy = pc ? pc[y] : (T)0;
     const cx<T> fy = foc ? foc[y] : cx<T>{(T)1, (T)0};
-    sfor<0, B>([&](auto bc) {
-        constexpr int b = decltype(bc)::value;
-        sfor<0, R>([&](auto rc) {
-            constexpr int r = decltype(rc)::value;
-            constexpr int i = b * R + r;
+    const int h = kind == AP_SUPERGAUSS ? d.ap_half_order : 1;
+    // the lane's points in chunks of CH: the aperture of a chunk is computed
+    // right before its points are used, so only CH aperture values and
+    // radii are live at a time
+    constexpr int CH = 4;
+    static_assert(P % CH == 0, "points per lane must be a multiple of the chunk");
+    sfor<0, P / CH>([&](auto cc) {
+        constexpr int c0 = decltype(cc)::value * CH;
+        // aperture amplitude A(x, y) of the chunk
+        T A[CH];
+        if (kind == AP_MASK) {
+            sfor<0, CH>([&](auto jc) {
+                constexpr int i = c0 + decltype(jc)::value;
+                A[decltype(jc)::value] =
+                    gld<T>(d.mask, row + (unsigned)sizeof(T) * (unsigned)reg_pos<S, R>(lane, i / R, i % R));
+            });
+        } else if (kind == AP_NONE) {
+            sfor<0, CH>([&](auto jc) { A[decltype(jc)::value] = (T)1; });
+        } else {
+            // u = r^2/r0^2 (super-Gaussian) or r^2/(2 r0^2) (Gaussian); exponent
+            // u^h, h = order/2, by squaring (a loop uniform across lanes)
+            T u[CH];
+            sfor<0, CH>([&](auto jc) {
+                constexpr int j = decltype(jc)::value, i = c0 + j;
+                const T X = ((T)reg_pos<S, R>(lane, i / R, i % R) - half) * dx;
+                u[j] = fma_(X, X, Y2) * ir;
+                A[j] = (T)1;
+            });
+            for (int e = h; e; e >>= 1) {
+                if (e & 1) sfor<0, CH>([&](auto jc) { A[decltype(jc)::value] *= u[decltype(jc)::value]; });
+                sfor<0, CH>([&](auto jc) { u[decltype(jc)::value] *= u[decltype(jc)::value]; });
+            }
+            sfor<0, CH>([&](auto jc) { A[decltype(jc)::value] = ex(-A[decltype(jc)::value]); });
+        }
+        sfor<0, CH>([&](auto jc) {
+            constexpr int j = decltype(jc)::value, i = c0 + j;
+            constexpr int b = i / R, r = i % R;
             const unsigned x = (unsigned)reg_pos<S, R>(lane, b, r);
             const cx<T> e = v[i];
             const T n = nv[i];
@@ -314,8 +322,8 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
             T eh;
             if constexpr (LS == 2) eh = ex((T)0.5 * n * iT1 / (iT1 + I));
             else eh = ex((T)0.5 * n);
-            const T A2 = A[i] * A[i];
-            const T aeh = A[i] * eh;
+            const T A2 = A[j] * A[j];
+            const T aeh = A[j] * eh;
             // bookkeeping in FP64 from the first term: a product of two
             // FP32 values is exact in FP64
             const double Id = (double)I;
@@ -443,8 +451,10 @@ __device__ __forceinline__ void row_task(const CavDesc& d, int rb, cx<T>* lds, d
 
 // PROP: propagator form of the column pass -- PROP_TABLE multiplies by the
 // FP64-built separable table hx(p) hx(q); PROP_PHASE evaluates the phase
-// pi lambda L (fx^2 + fy^2) in the field's precision (the plain form).
-enum : int { PROP_TABLE = 0, PROP_PHASE = 1 };
+// pi lambda L (fx^2 + fy^2) in the field's precision (the plain form);
+// PROP_TRANS multiplies by a general N x N transfer function (the map with
+// kernel K of Eq. (10)), read by column: 8 more bytes per point.
+enum : int { PROP_TABLE = 0, PROP_PHASE = 1, PROP_TRANS = 2 };
 
 // Column-task registers; with HXREG the task's propagator table hx travels
 // with the tile (HX_IT 16-byte chunks per thread) and is committed to LDS.
@@ -540,6 +550,17 @@ __device__ __forceinline__ void col_body(const CavDesc& d, int cb, cx<T>* lds, C
                     T s, co;
                     sc((T)(px2 + q * q) * c, &s, &co);
                     v[b * RL + r] = cmul(v[b * RL + r], cx<T>{co * inn, -s * inn});
+                });
+            });
+        } else if constexpr (PROP == PROP_TRANS) {
+            // column kx of the transfer table: N contiguous entries
+            const cx<T>* tt = static_cast<const cx<T>*>(d.trans);
+            const unsigned col = (unsigned)kx * (unsigned)S::N * (unsigned)sizeof(cx<T>);
+            sfor<0, B>([&](auto bc) {
+                sfor<0, RL>([&](auto rc) {
+                    constexpr int b = decltype(bc)::value, r = decltype(rc)::value;
+                    const unsigned q = (unsigned)reg_pos<S, RL>(lane, b, r);
+                    v[b * RL + r] = cmul(v[b * RL + r], gld<cx<T>>(tt, col + (unsigned)sizeof(cx<T>) * q));
                 });
             });
         } else if constexpr (HXREG) {

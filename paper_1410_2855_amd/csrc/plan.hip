@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <vector>
 
@@ -20,6 +21,20 @@ int set_err(int code, const char* fmt, ...) {
     vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
     return code;
+}
+
+// Allocations left before a forced failure (-1: none forced).
+static std::atomic<int> g_fail_after{-1};
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+    int left = g_fail_after.load();
+    while (left >= 0 && !g_fail_after.compare_exchange_weak(left, left - 1)) {
+    }
+    if (left == 0) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
 }
 
 static constexpr double kTwoPi = 6.283185307179586476925286766559;
@@ -121,7 +136,7 @@ static int upload(void** dst, const std::vector<double>& v, bool as_float) {
     const size_t n = v.size();
     if (n == 0) { *dst = nullptr; return LSR_OK; }
     const size_t bytes = n * (as_float ? sizeof(float) : sizeof(double));
-    if (hipMalloc(dst, bytes) != hipSuccess) {
+    if (dev_malloc(dst, bytes) != hipSuccess) {
         *dst = nullptr;
         (void)hipGetLastError();
         return set_err(LSR_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
@@ -139,7 +154,7 @@ static int upload(void** dst, const std::vector<double>& v, bool as_float) {
 template <typename P>
 static int dalloc(P** dst, size_t bytes) {
     void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    if (dev_malloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         *dst = nullptr;
         return set_err(LSR_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
@@ -153,7 +168,7 @@ static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 static void free_plan_memory(lsr_plan_s* p) {
     void* bufs[] = {p->d_tw, p->d_hx, p->d_pump, p->d_foc, p->d_partials, p->d_trace,
                     p->d_counters, p->d_scratch, p->d_radial_part, p->d_diag_out, p->d_hz,
-                    p->d_hs, p->d_rough};
+                    p->d_hs, p->d_rough, p->d_trans};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -229,6 +244,8 @@ static CavDesc sheet_desc(const lsr_plan_s* p, void* E, void* Ninv, int k) {
     return d;
 }
 
+CavDesc plan_sheet_desc(const lsr_plan_s* p, void* E, void* Ninv, int k) { return sheet_desc(p, E, Ninv, k); }
+
 // The launches of n >= 1 round trips, in order: the first row pass, then per
 // trip and sheet the column pass and the row pass of the next sheet; the last
 // row pass only finishes the inverse transform.  Sheet 0's column pass folds
@@ -254,6 +271,12 @@ using namespace lsr;
 extern "C" {
 
 const char* lsr_last_error(void) { return g_err; }
+
+int lsr_test_fail_alloc(int after) {
+    if (after < -1) return set_err(LSR_EINVAL, "after must be >= -1");
+    g_fail_after.store(after);
+    return LSR_OK;
+}
 
 const char* lsr_version(void) { return "lsr 0.1.0 gfx950"; }
 
@@ -335,6 +358,9 @@ int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L, do
     p->trace_cap = trace_capacity();
     const bool f32 = prec != LSR_PREC_FP64;
     const int nrb = N / p->shape.LPW;
+    // row blocks of the narrowest shape a plan of this size can take (lines
+    // per workgroup >= 2), so the partials and spectrum scratch fit any
+    const int nrb_max = N / 2;
     int rc = LSR_OK;
     auto fail = [&](int code) {
         free_plan_memory(p);
@@ -347,7 +373,7 @@ int lsr_plan_create(lsr_plan* out, int N, double dx, double lambda, double L, do
     const bool curved = F != 0.0 && std::isfinite(F);
     if (curved)
         if ((rc = upload(&p->d_foc, build_focal(N, dx, lambda, F), f32))) return fail(rc);
-    if ((rc = dalloc(&p->d_partials, sizeof(double) * 4 * (size_t)nrb))) return fail(rc);
+    if ((rc = dalloc(&p->d_partials, sizeof(double) * 4 * (size_t)nrb_max))) return fail(rc);
     if ((rc = dalloc(&p->d_trace, sizeof(double) * 4 * (size_t)p->trace_cap))) return fail(rc);
     if ((rc = dalloc(&p->d_counters, sizeof(unsigned) * CNT_WORDS))) return fail(rc);
     if (hipMemset(p->d_counters, 0, sizeof(unsigned) * CNT_WORDS) != hipSuccess ||
@@ -454,7 +480,70 @@ int lsr_plan_set_filter(lsr_plan p, double delta) {
     p->d_hs = ts;
     p->filter = delta;
     p->d.hx = t;
-    p->d.prop_kind = delta > 0 ? 1 : 0;
+    p->d.prop_kind = p->d_trans ? 2 : delta > 0 ? 1 : 0;
+    ++p->version;
+    return LSR_OK;
+}
+
+int lsr_plan_set_fft_plan(lsr_plan p, int k) {
+    if (!p) return set_err(LSR_EINVAL, "plan is NULL");
+    if (k < 0) return set_err(LSR_EINVAL, "FFT plan %d", k);
+    const Launchers* kern = k == 0 ? launchers_for(p->N, p->prec == PREC_FP64)
+                                   : (p->prec == PREC_FP64 ? nullptr : launchers_alt(p->N, k));
+    if (!kern) return set_err(LSR_EUNSUPPORTED, "no one-cavity FFT plan %d for N=%d in this precision form", k, p->N);
+    if (k == p->fft_plan) return LSR_OK;
+    DeviceGuard g(p->device);
+    void* t = nullptr;
+    int rc = upload(&t, build_twiddles(kern->shape, p->prec == PREC_PLAIN, p->prec != PREC_FP64), p->prec != PREC_FP64);
+    if (rc) return rc;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) {
+        (void)hipFree(t);
+        return set_err(LSR_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    // the old table is no longer read by enqueued work
+    (void)hipFree(p->d_tw);
+    p->d_tw = t;
+    p->d.tw = t;
+    p->kern = kern;
+    p->shape = kern->shape;
+    p->d.nrb = p->N / p->shape.LPW;
+    p->fft_plan = k;
+    ++p->version;
+    return LSR_OK;
+}
+
+int lsr_plan_set_transfer(lsr_plan p, const double* T) {
+    if (!p) return set_err(LSR_EINVAL, "plan is NULL");
+    const int N = p->N;
+    const size_t nn = (size_t)N * (size_t)N;
+    void* t = nullptr;
+    if (T) {
+        if (p->slices != 1) return set_err(LSR_EINVAL, "a general transfer function needs a single gain sheet");
+        // by column (frequency p, q at p*N + q), 1/N^2 folded in
+        std::vector<double> tab(2 * nn);
+        const double inn = 1.0 / ((double)N * (double)N);
+        for (int q = 0; q < N; ++q)
+            for (int pp = 0; pp < N; ++pp) {
+                const size_t src = 2 * ((size_t)q * N + pp), dst = 2 * ((size_t)pp * N + q);
+                if (!std::isfinite(T[src]) || !std::isfinite(T[src + 1]))
+                    return set_err(LSR_EINVAL, "transfer value (%d, %d) is not finite", q, pp);
+                tab[dst] = T[src] * inn;
+                tab[dst + 1] = T[src + 1] * inn;
+            }
+        DeviceGuard g(p->device);
+        int rc = upload(&t, tab, p->prec != PREC_FP64);
+        if (rc) return rc;
+    }
+    DeviceGuard g(p->device);
+    if (hipStreamSynchronize(p->stream) != hipSuccess) {
+        if (t) (void)hipFree(t);
+        return set_err(LSR_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    // the old table is no longer read by enqueued work
+    if (p->d_trans) (void)hipFree(p->d_trans);
+    p->d_trans = t;
+    p->d.trans = t;
+    p->d.prop_kind = t ? 2 : p->filter > 0 ? 1 : 0;
     ++p->version;
     return LSR_OK;
 }
@@ -494,6 +583,7 @@ int lsr_plan_set_roughness(lsr_plan p, const double* psi) {
 int lsr_plan_set_slices(lsr_plan p, int m) {
     if (!p) return set_err(LSR_EINVAL, "plan is NULL");
     if (m < 1 || m > LSR_MAX_SLICES) return set_err(LSR_EINVAL, "%d gain sheets: must be 1..%d", m, LSR_MAX_SLICES);
+    if (m > 1 && p->d_trans) return set_err(LSR_EINVAL, "several gain sheets do not combine with a general transfer function");
     DeviceGuard g(p->device);
     void* ts = nullptr;
     int rc = build_sheet_table(p, m, p->filter, &ts);
@@ -637,13 +727,22 @@ int lsr_diag(lsr_plan p, const void* E, const void* Ninv, lsr_diag_out* out) {
     if (!p || !out) return set_err(LSR_EINVAL, "plan or out is NULL");
     if (!E || !Ninv || !aligned16(E) || !aligned16(Ninv)) return set_err(LSR_EINVAL, "bad E/Ninv pointer");
     DeviceGuard g(p->device);
-    const int N = p->N, nb = p->d.nbins, nrb = p->d.nrb;
+    const int N = p->N, nb = p->d.nbins, nrb = N / 2;   // as many row blocks as any shape has
     const size_t elem = 2 * p->real_bytes();
     int rc;
+    // the spectrum scratch, on first use; all three or none
     if (!p->d_scratch) {
-        if ((rc = dalloc(&p->d_scratch, elem * (size_t)N * N))) return rc;
-        if ((rc = dalloc(&p->d_radial_part, sizeof(double) * (size_t)nrb * nb))) return rc;
-        if ((rc = dalloc(&p->d_diag_out, sizeof(double) * (4 + (size_t)nb)))) return rc;
+        void* sc = nullptr;
+        double *rp = nullptr, *dout = nullptr;
+        if ((rc = dalloc(&sc, elem * (size_t)N * N)) || (rc = dalloc(&rp, sizeof(double) * (size_t)nrb * nb)) ||
+            (rc = dalloc(&dout, sizeof(double) * (4 + (size_t)nb)))) {
+            if (sc) (void)hipFree(sc);
+            if (rp) (void)hipFree(rp);
+            return rc;
+        }
+        p->d_scratch = sc;
+        p->d_radial_part = rp;
+        p->d_diag_out = dout;
     }
     CavDesc d = p->d;
     d.E = const_cast<void*>(E);

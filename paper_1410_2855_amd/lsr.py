@@ -57,6 +57,8 @@ _SIGS = {
     "lsr_plan_set_model": (_i, [_vp, _i]),
     "lsr_plan_set_slices": (_i, [_vp, _i]),
     "lsr_plan_set_roughness": (_i, [_vp, _vp]),
+    "lsr_plan_set_transfer": (_i, [_vp, _vp]),
+    "lsr_plan_set_fft_plan": (_i, [_vp, _i]),
     "lsr_propagate": (_i, [_vp, _vp, _d, _vp]),
     "lsr_plan_set_stream": (_i, [_vp, _vp]),
     "lsr_roundtrips": (_i, [_vp, _vp, _vp, _i]),
@@ -77,6 +79,7 @@ _SIGS = {
     "lsr_batch_destroy": (None, [_vp]),
     "lsr_autotune": (_i, [_vp, _vp, ctypes.c_char_p]),
     "lsr_last_error": (ctypes.c_char_p, []),
+    "lsr_test_fail_alloc": (_i, [_i]),
     "lsr_version": (ctypes.c_char_p, []),
     "lsr_supported": (_i, [_i, _i]),
     "lsr_fft_shape": (_i, [_i, _i, ctypes.POINTER(_i), _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
@@ -131,6 +134,10 @@ def _stream_handle(stream) -> int:
 
 def lsr_last_error() -> str:
     return load().lsr_last_error().decode()
+
+
+def lsr_test_fail_alloc(after: int):
+    _check(load().lsr_test_fail_alloc(after))
 
 
 def lsr_version() -> str:
@@ -200,6 +207,20 @@ def lsr_plan_set_roughness(plan, psi):
         return
     a = np.ascontiguousarray(psi, dtype=np.float64)
     _check(load().lsr_plan_set_roughness(plan, a.ctypes.data))
+
+
+def lsr_plan_set_fft_plan(plan, k: int):
+    _check(load().lsr_plan_set_fft_plan(plan, int(k)))
+
+
+def lsr_plan_set_transfer(plan, T):
+    """T: host N x N complex transfer function of a general nonlocal step
+    (frequency order, row = y frequency), or None for the propagator."""
+    if T is None:
+        _check(load().lsr_plan_set_transfer(plan, None))
+        return
+    a = np.ascontiguousarray(T, dtype=np.complex128)
+    _check(load().lsr_plan_set_transfer(plan, a.ctypes.data))
 
 
 def lsr_propagate(plan, E_in, z: float, E_out):
@@ -327,17 +348,22 @@ class Plan:
         self.handle = lsr_plan_create(cav.N, cav.dx, cav.lam, cav.L, focal, cav.R,
                                       ap_kind=cav.ap_kind, ap_radius=cav.ap_radius,
                                       ap_order=cav.ap_order, prec=prec)
-        lsr_plan_set_gain(self.handle, cav.N0, cav.T1, cav.mod_amp, cav.mod_period)
-        if getattr(cav, "filter_delta", 0.0):
-            lsr_plan_set_filter(self.handle, cav.filter_delta)
-        if getattr(cav, "model", 0):
-            lsr_plan_set_model(self.handle, cav.model)
-        if getattr(cav, "slices", 1) != 1:
-            lsr_plan_set_slices(self.handle, cav.slices)
-        if getattr(cav, "rough_rms", 0.0):
-            from .inputs import rough_field
-            lsr_plan_set_roughness(self.handle, rough_field(cav))
-        lsr_plan_set_stream(self.handle, stream if stream is not None else torch.cuda.current_stream())
+        try:
+            lsr_plan_set_gain(self.handle, cav.N0, cav.T1, cav.mod_amp, cav.mod_period)
+            if getattr(cav, "filter_delta", 0.0):
+                lsr_plan_set_filter(self.handle, cav.filter_delta)
+            if getattr(cav, "model", 0):
+                lsr_plan_set_model(self.handle, cav.model)
+            if getattr(cav, "slices", 1) != 1:
+                lsr_plan_set_slices(self.handle, cav.slices)
+            if getattr(cav, "rough_rms", 0.0):
+                from .inputs import rough_field
+                lsr_plan_set_roughness(self.handle, rough_field(cav))
+            lsr_plan_set_stream(self.handle, stream if stream is not None else torch.cuda.current_stream())
+        except BaseException:
+            # a failed set-up leaves no plan behind
+            self.close()
+            raise
 
     @property
     def cdtype(self):

@@ -1,12 +1,16 @@
 """Long runs and full-size precision checks.
 
 The dynamics can be chaotic, so beyond 50 round trips only statistics are
-compared: over the last half of a run the output power's mean must agree
-within 1 % and its RMS fluctuation within 1 % of the mean, and the far-field
-spectrum averaged every 100 trips must peak in the same radial bin.  The
-reference for these long runs is the GPU's FP64 form of the map, which itself
-matches the FP64 CPU oracle to ~1e-11 over 50 trips (test_gpu_map.py); the
-CPU oracle would take hours here.
+compared over the last half of a run: the output power's mean and its RMS
+fluctuation must agree within 1 % of the mean, and the far-field spectrum
+averaged every 100 trips must peak in the same radial bin.  Where a window's
+own sampling noise exceeds that (bursty cavities whose power comes in
+irregular spikes), the bar is two standard errors of the difference, each
+estimated from ten blocks of the window: such a statistic is not fixed to 1 %
+by a 2500-trip window, and FP64 runs whose initial fields differ by 1e-5
+already spread by 2-4 % of the mean.  The reference for the long runs is the
+GPU's FP64 form of the map, which itself matches the FP64 CPU oracle to
+~1e-11 over 50 trips (test_gpu_map.py); the CPU oracle would take hours here.
 """
 import numpy as np
 import pytest
@@ -52,17 +56,54 @@ def long_run(cav, prec, trips, chunk=500, spec_every=100):
     return np.asarray(power), spec / max(nspec, 1)
 
 
-def stats_agree(p32, p64, s32, s64):
-    h = len(p64) // 2
-    a, b = p32[h:], p64[h:]
-    mean_a, mean_b = a.mean(), b.mean()
-    rms_a, rms_b = a.std(), b.std()
+def window_stats(power, blocks=10):
+    """Mean and RMS fluctuation of the last half of a power series, and their
+    standard errors from `blocks` equal blocks of that window (block means,
+    and block mean squares about the window mean)."""
+    a = np.asarray(power)[len(power) // 2:]
+    mean, rms = a.mean(), a.std()
+    parts = np.array_split(a, blocks)
+    se_mean = np.std([b.mean() for b in parts], ddof=1) / np.sqrt(blocks)
+    var_b = np.array([np.mean((b - mean) ** 2) for b in parts])
+    se_rms = np.std(var_b, ddof=1) / np.sqrt(blocks) / (2 * rms) if rms > 0 else 0.0
+    return mean, rms, se_mean, se_rms
+
+
+def stats_agree(p32, p64, s32, s64, label=""):
+    m_a, r_a, sm_a, sr_a = window_stats(p32)
+    m_b, r_b, sm_b, sr_b = window_stats(p64)
+    bar_m = max(0.01 * m_b, 2 * np.hypot(sm_a, sm_b))
+    bar_r = max(0.01 * m_b, 2 * np.hypot(sr_a, sr_b))
     dom_a = 1 + int(np.argmax(s32[1:]))
     dom_b = 1 + int(np.argmax(s64[1:]))
-    print("mean %.6e vs %.6e, rms %.4e vs %.4e, dominant bin %d vs %d" % (mean_a, mean_b, rms_a, rms_b, dom_a, dom_b))
-    assert abs(mean_a - mean_b) <= 0.01 * mean_b
-    assert abs(rms_a - rms_b) <= 0.01 * mean_b
-    assert dom_a == dom_b
+    print("%s mean %.6e vs %.6e (bar %.2f%%), rms %.4e vs %.4e (diff %.2f%%, bar %.2f%% of the mean), "
+          "dominant bin %d vs %d" % (label, m_a, m_b, 100 * bar_m / m_b, r_a, r_b, 100 * abs(r_a - r_b) / m_b,
+                                     100 * bar_r / m_b, dom_a, dom_b))
+    assert abs(m_a - m_b) <= bar_m, label
+    assert abs(r_a - r_b) <= bar_r, label
+    assert dom_a == dom_b, label
+
+
+def batched_long_run(cavs, trips, every=100):
+    """All cavities batched in the FP32 form: each one's output power per trip
+    and its spectrum averaged every `every` trips over the last half."""
+    plans = [lsr.Plan(c) for c in cavs]
+    st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+    Es, Ns = [x[0] for x in st], [x[1] for x in st]
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    power = [[] for _ in cavs]
+    spec = [np.zeros(lsr.lsr_plan_nbins(p.handle)) for p in plans]
+    for k in range(trips // every):
+        lsr.lsr_batch_roundtrips(b, Es, Ns, every)
+        for i, (p, c) in enumerate(zip(plans, cavs)):
+            power[i].extend((1 - c.R) * p.trace(every)[:, 2] * c.dx ** 2)
+            if (k + 1) * every > trips // 2:
+                spec[i] += lsr.lsr_batch_diag(b, i, Es[i], Ns[i], spec[i].size)["radial"]
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.sync()
+        p.close()
+    return [np.asarray(x) for x in power], spec
 
 
 def test_long_run_256_against_the_oracle():
@@ -90,59 +131,48 @@ def test_long_run_256_against_the_oracle():
     stats_agree(np.asarray(pg), np.asarray(po), sg, so)
 
 
-def test_long_run_batched_sweep_vs_fp64():
-    """The batched sweep's cavities (uneven N, F, pump, T1, R), 5000 round trips
-    batched in the FP32 form against each cavity alone in the GPU FP64 form:
-    power statistics over the last half and the dominant bin of the spectrum
-    averaged every 100 trips, for the first 64 cavities of the sweep."""
-    trips, every = 5000, 100
-    cavs = sweep(512)[:64]
-    plans = [lsr.Plan(c) for c in cavs]
-    st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
-    Es, Ns = [x[0] for x in st], [x[1] for x in st]
-    b = lsr.lsr_batch_create([p.handle for p in plans])
-    power = [[] for _ in cavs]
-    spec = [np.zeros(lsr.lsr_plan_nbins(p.handle)) for p in plans]
-    for k in range(trips // every):
-        lsr.lsr_batch_roundtrips(b, Es, Ns, every)
-        for i, (p, c) in enumerate(zip(plans, cavs)):
-            power[i].extend((1 - c.R) * p.trace(every)[:, 2] * c.dx ** 2)
-            if (k + 1) * every > trips // 2:
-                spec[i] += lsr.lsr_batch_diag(b, i, Es[i], Ns[i], spec[i].size)["radial"]
-    lsr.lsr_batch_destroy(b)
-    for p in plans:
-        p.sync()
-        p.close()
-    for i, c in enumerate(cavs):
-        p64, s64 = long_run(c, lsr.LSR_PREC_FP64, trips, chunk=trips, spec_every=every)
-        stats_agree(np.asarray(power[i]), p64, spec[i], s64)
+SWEEP_TRIPS = 5000
 
 
-def test_long_run_structured_4096_batched_vs_fp64():
-    """16 x 4096^2 with the periodic pump: two of the cavities, 5000 round trips
-    batched in the FP32 form against each alone in the GPU FP64 form."""
-    trips, every = 5000, 100
-    cavs = structured_4096()[:2]
-    plans = [lsr.Plan(c) for c in cavs]
-    st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
-    Es, Ns = [x[0] for x in st], [x[1] for x in st]
-    b = lsr.lsr_batch_create([p.handle for p in plans])
-    power = [[] for _ in cavs]
-    spec = [np.zeros(lsr.lsr_plan_nbins(p.handle)) for p in plans]
-    for k in range(trips // every):
-        lsr.lsr_batch_roundtrips(b, Es, Ns, every)
-        for i, (p, c) in enumerate(zip(plans, cavs)):
-            power[i].extend((1 - c.R) * p.trace(every)[:, 2] * c.dx ** 2)
-            if (k + 1) * every > trips // 2:
-                spec[i] += lsr.lsr_batch_diag(b, i, Es[i], Ns[i], spec[i].size)["radial"]
-    lsr.lsr_batch_destroy(b)
-    for p in plans:
-        p.sync()
-        p.close()
-    del Es, Ns, st
-    for i, c in enumerate(cavs):
-        p64, s64 = long_run(c, lsr.LSR_PREC_FP64, trips, chunk=trips, spec_every=every)
-        stats_agree(np.asarray(power[i]), p64, spec[i], s64)
+@pytest.fixture(scope="module")
+def sweep_fp32():
+    """The whole 512-cavity sweep batched in the FP32 form for 5000 trips."""
+    cavs = sweep(512)
+    power, spec = batched_long_run(cavs, SWEEP_TRIPS)
+    return cavs, power, spec
+
+
+@pytest.mark.parametrize("part", range(8))
+def test_long_run_batched_sweep_vs_fp64(sweep_fp32, part):
+    """The batched sweep's cavities (uneven N, F, pump, T1, R), 5000 round
+    trips batched in the FP32 form, all 512 in one batch, against each cavity
+    alone in the GPU FP64 form: power statistics over the last half and the
+    dominant bin of the spectrum averaged every 100 trips; cavities
+    64 part .. 64 part + 63."""
+    cavs, power, spec = sweep_fp32
+    for i in range(64 * part, 64 * part + 64):
+        p64, s64 = long_run(cavs[i], lsr.LSR_PREC_FP64, SWEEP_TRIPS, chunk=SWEEP_TRIPS, spec_every=100)
+        stats_agree(power[i], p64, spec[i], s64, "sweep cavity %d (N=%d)" % (i, cavs[i].N))
+
+
+@pytest.fixture(scope="module")
+def structured_fp32():
+    """All 16 structured-gain cavities at 4096^2 batched in the FP32 form for
+    5000 trips."""
+    cavs = structured_4096()
+    power, spec = batched_long_run(cavs, SWEEP_TRIPS)
+    return cavs, power, spec
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_long_run_structured_4096_batched_vs_fp64(structured_fp32, part):
+    """16 x 4096^2 with the periodic pump, 5000 round trips batched in the
+    FP32 form against each cavity alone in the GPU FP64 form; cavities
+    4 part .. 4 part + 3."""
+    cavs, power, spec = structured_fp32
+    for i in range(4 * part, 4 * part + 4):
+        p64, s64 = long_run(cavs[i], lsr.LSR_PREC_FP64, SWEEP_TRIPS, chunk=SWEEP_TRIPS, spec_every=100)
+        stats_agree(power[i], p64, spec[i], s64, "structured cavity %d (M=%d)" % (i, cavs[i].mod_periods))
 
 
 def test_long_run_1024_fp32_vs_fp64():

@@ -256,3 +256,54 @@ def test_bad_arguments_on_device():
         lsr.lsr_roundtrips(p.handle, int(e.data_ptr()) + 8, n, 1)
     assert ei.value.code == lsr.LSR_EINVAL
     p.close()
+
+
+@pytest.mark.parametrize("N", [256, 1024, 2048])
+def test_one_cavity_fft_plan_with_eight_points_per_lane(N, tmp_path):
+    """The one-cavity FFT plan with 8 points per lane computes the same map:
+    50 trips against the oracle at the usual bar, 3 trips against the default
+    plan to FP32 rounding; a batch holding such a plan runs its own plan and
+    stays bitwise the default one-cavity path; the autotuner picks one of the
+    two and records it; FP64 plans and other sizes have none."""
+    from paper_1410_2855_amd.inputs import Cavity
+
+    cav = Cavity(N=N, F=200.0 if N < 2048 else 1000.0, R=0.9, pump_ratio=2.5, T1=600.0, index=9)
+    e0, n0 = initial_state(cav)
+    p = lsr.Plan(cav)
+    lsr.lsr_plan_set_fft_plan(p.handle, 1)
+    trips = 50 if N < 2048 else 20
+    e, n = p.state(e0, n0)
+    p.roundtrips(e, n, trips)
+    p.sync()
+    eo, no, to = oracle.run(oracle_params(cav), e0, n0, trips)
+    assert rel(e.cpu().numpy(), eo) <= 1e-5 and rel(n.cpu().numpy(), no) <= 1e-5
+    assert rel(p.trace(trips), to) <= 1e-5
+    q = lsr.Plan(cav)
+    e1, n1 = p.state(e0, n0)
+    e2, n2 = q.state(e0, n0)
+    p.roundtrips(e1, n1, 3)
+    q.roundtrips(e2, n2, 3)
+    torch.cuda.synchronize()
+    assert rel(e1.cpu().numpy(), e2.cpu().numpy()) <= 2e-6
+    # a batch runs its group's plan whatever the plan's own
+    e3, n3 = p.state(e0, n0)
+    b = lsr.lsr_batch_create([p.handle])
+    lsr.lsr_batch_roundtrips(b, [e3], [n3], 3)
+    torch.cuda.synchronize()
+    assert torch.equal(e3, e2) and torch.equal(n3, n2)
+    lsr.lsr_batch_destroy(b)
+    cache = str(tmp_path / "tune.json")
+    lsr.lsr_autotune(q.handle, None, cache)
+    import json
+    assert json.load(open(cache))["gfx950:plan:%d:1" % N]["shape"] in (0, 1)
+    f = lsr.Plan(cav, prec=lsr.LSR_PREC_FP64)
+    with pytest.raises(lsr.LsrError) as ei:
+        lsr.lsr_plan_set_fft_plan(f.handle, 1)
+    assert ei.value.code == lsr.LSR_EUNSUPPORTED
+    for x in (p, q, f):
+        x.close()
+    r = lsr.Plan(cav.with_(N=512))
+    with pytest.raises(lsr.LsrError) as ei:
+        lsr.lsr_plan_set_fft_plan(r.handle, 1)
+    assert ei.value.code == lsr.LSR_EUNSUPPORTED
+    r.close()

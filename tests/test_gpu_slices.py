@@ -113,7 +113,74 @@ def test_timed_launches_advance_like_roundtrips_and_diag_reads_sheet_zero():
     p.close()
 
 
-def test_batches_refuse_several_sheets_and_bad_counts():
+def _sheet_batch(cavs):
+    plans = [lsr.Plan(c) for c in cavs]
+    st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+    return plans, [x[0] for x in st], [x[1] for x in st]
+
+
+def _one_cavity(cavs, trips):
+    out = []
+    for c in cavs:
+        p = lsr.Plan(c)
+        e, n = p.state(*initial_state(c))
+        p.roundtrips(e, n, trips)
+        p.sync()
+        out.append((e.clone(), n.clone(), p.trace(trips)))
+        p.close()
+    return out
+
+
+@pytest.mark.parametrize("m,sizes,engine,k", [
+    (2, (512, 1024), 1, 4),     # grouped passes, whole-call graphs
+    (3, (256, 768), 1, 2),      # k-trip and remainder graphs
+    (2, (512, 1024), 0, 3),     # persistent kernel per sheet step
+    (3, (1024,), 2, 0),         # software-pipelined grouped passes, eager
+])
+def test_batched_sheets_are_bitwise_the_one_cavity_path(m, sizes, engine, k):
+    """Batches of cavities with m gain sheets each (every plan of a batch has
+    the same m): every sheet step is one grouped row pass and one grouped
+    column pass over all cavities (or one persistent launch), the column
+    pass of sheet 0 folding the trip's sums; bitwise the one-cavity path."""
+    cavs = [c.with_(slices=m, model=c.index % 3) for c in sweep(4, seed=7, sizes=sizes)]
+    trips = 7
+    ref = _one_cavity(cavs, trips)
+    plans, Es, Ns = _sheet_batch(cavs)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_configure(b, engine=engine, graph_k=k)
+    lsr.lsr_batch_roundtrips(b, Es, Ns, 3)
+    lsr.lsr_batch_roundtrips(b, Es, Ns, trips - 3)
+    for p in plans:
+        p.sync()
+    for i, (p, e, n) in enumerate(zip(plans, Es, Ns)):
+        assert torch.equal(e, ref[i][0]) and torch.equal(n, ref[i][1]), i
+        assert np.array_equal(p.trace(trips - 3), ref[i][2][3:]), i
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
+
+
+def test_batched_sheets_fifty_steps_against_the_oracle():
+    """Batched sheets held to the single-sheet bar at the same number of
+    nonlocal steps, as the one-cavity sheets above: 50 steps of m = 3 sheets
+    are 16 round trips."""
+    cavs = [sheets(3, N=384), sheets(3, N=512).with_(index=56, model=1)]
+    trips = 50 // 3
+    plans, Es, Ns = _sheet_batch(cavs)
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_roundtrips(b, Es, Ns, trips)
+    for p in plans:
+        p.sync()
+    for c, p, e, n in zip(cavs, plans, Es, Ns):
+        eo, no, to = oracle.run(oracle_params(c), *initial_state(c), trips)
+        assert rel(e.cpu().numpy(), eo) <= 1e-5 and rel(n.cpu().numpy(), no) <= 1e-5
+        assert rel(p.trace(trips), to) <= 1e-5
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
+
+
+def test_batches_need_one_sheet_count_and_bad_counts_are_refused():
     cavs = sweep(2, seed=3, sizes=(512,))
     plans = [lsr.Plan(c) for c in cavs]
     st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
@@ -122,10 +189,18 @@ def test_batches_refuse_several_sheets_and_bad_counts():
     with pytest.raises(lsr.LsrError) as ei:
         lsr.lsr_batch_roundtrips(b, [s[0] for s in st], [s[1] for s in st], 1)
     assert ei.value.code == lsr.LSR_EUNSUPPORTED
-    lsr.lsr_batch_destroy(b)
     with pytest.raises(lsr.LsrError) as ei:
         lsr.lsr_batch_create([p.handle for p in plans])
     assert ei.value.code == lsr.LSR_EUNSUPPORTED
+    # the same count on every plan: the batch regroups and runs
+    lsr.lsr_plan_set_slices(plans[1].handle, 2)
+    n2 = [torch.cat([s[1].unsqueeze(0)] * 2).contiguous() / 2 for s in st]
+    lsr.lsr_batch_roundtrips(b, [s[0] for s in st], n2, 2)
+    with pytest.raises(lsr.LsrError) as ei:
+        lsr.lsr_batch_time_kernels(b, [s[0] for s in st], n2, 2)
+    assert ei.value.code == lsr.LSR_EUNSUPPORTED
+    torch.cuda.synchronize()
+    lsr.lsr_batch_destroy(b)
     for bad in (0, -2, lsr.LSR_MAX_SLICES + 1):
         with pytest.raises(lsr.LsrError) as ei:
             lsr.lsr_plan_set_slices(plans[1].handle, bad)
