@@ -252,6 +252,30 @@ int lsr_plan_set_stream(lsr_plan p, void* hip_stream);
  * plus 1.  The per-trip diagnostics sums go to the plan's trace ring. */
 int lsr_roundtrips(lsr_plan p, void* E, void* Ninv, int n_trips);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the round
+ * trips of lsr_roundtrips in the FP64TAB form without a plan, and without any
+ * allocation.  The arguments are those of lsr_plan_create (N, dx, lambda, L,
+ * F, R, ap), lsr_plan_set_gain (N0, T1, mod_amp, mod_period) and
+ * lsr_plan_set_model (model), then E (device complex64 N*N) and Ninv (device
+ * float N*N) as for lsr_roundtrips, n_trips >= 0, trace (device, 4*n_trips
+ * doubles receiving each trip's S1..S4 as lsr_trace returns them, or NULL)
+ * and the stream (hipStream_t as void*, NULL = null stream).
+ * The FP64-built tables, the per-row-block partial sums and the counters live
+ * in a file-scope device array of 512 KiB that each GPU holds until the
+ * process ends; a small kernel rebuilds the tables and clears the counters at
+ * the start of every call, then the call enqueues the launches of
+ * lsr_roundtrips (kernel launches only: no allocation, copy, memset or
+ * synchronisation).  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (on different streams, or from several threads)
+ * race and give wrong results.  No mirror roughness and one gain sheet; the
+ * non-finite state is not reported (the trace shows it).  LSR_EINVAL for bad
+ * arguments or a size whose tables exceed the array, LSR_EUNSUPPORTED for N
+ * not compiled in. */
+int lsr_roundtrips_static(int N, double dx, double lambda, double L, double F, double R,
+                          const lsr_aperture* ap, double N0, double T1, double mod_amp, double mod_period,
+                          int model, void* E, void* Ninv, int n_trips, double* trace, void* stream);
+
 /* Wait for the plan's stream; LSR_ENONFINITE if any trip since the last
  * lsr_sync saw a non-finite state (the flag is cleared by the report). */
 int lsr_sync(lsr_plan p);

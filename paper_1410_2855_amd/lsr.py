@@ -62,6 +62,8 @@ _SIGS = {
     "lsr_propagate": (_i, [_vp, _vp, _d, _vp]),
     "lsr_plan_set_stream": (_i, [_vp, _vp]),
     "lsr_roundtrips": (_i, [_vp, _vp, _vp, _i]),
+    "lsr_roundtrips_static": (_i, [_i, _d, _d, _d, _d, _d, ctypes.POINTER(lsr_aperture), _d, _d, _d, _d, _i,
+                                   _vp, _vp, _i, _vp, _vp]),
     "lsr_sync": (_i, [_vp]),
     "lsr_time_kernels": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(_d)]),
     "lsr_trace": (_i, [_vp, ctypes.POINTER(_d), _i]),
@@ -233,6 +235,14 @@ def lsr_plan_set_stream(plan, stream):
 
 def lsr_roundtrips(plan, E, Ninv, n_trips: int):
     _check(load().lsr_roundtrips(plan, _ptr(E), _ptr(Ninv), n_trips))
+
+
+def lsr_roundtrips_static(N, dx, lam, L, F, R, ap, N0, T1, mod_amp, mod_period, model, E, Ninv, n_trips,
+                          trace=None, stream=None):
+    """The allocation-free form of lsr_roundtrips (no plan): ap is an
+    lsr_aperture, trace None or a device float64 tensor of 4 n_trips values."""
+    _check(load().lsr_roundtrips_static(N, dx, lam, L, F, R, ctypes.byref(ap), N0, T1, mod_amp, mod_period, model,
+                                        _ptr(E), _ptr(Ninv), n_trips, _ptr(trace), _stream_handle(stream)))
 
 
 def lsr_time_kernels(plan, E, Ninv, n_trips: int):
