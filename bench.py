@@ -282,7 +282,7 @@ def summarize_ea(out_dir: str, workload: str, cavities: int, grid: int, workload
             txt.append("  the copy moves %.1f MiB each way" % (COPY_BYTES / 2 ** 20))
         else:
             txt.append("  requests: %.3f x algorithmic (%d B)" % ((rd + wr) / algo[k], algo[k]))
-            if k in cal:
+            if k in cal and cal[k].get("points_per_launch") == pts:
                 txt.append("  copy-calibrated FETCH_SIZE + WRITE_SIZE (profiles/traffic.json): %.3f x algorithmic"
                            % (cal[k]["bytes_per_launch"] / algo[k]))
     txt.append("")

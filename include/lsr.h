@@ -164,11 +164,9 @@ int lsr_propagate(lsr_plan p, const void* E_in, double z, void* E_out);
 int lsr_plan_set_filter(lsr_plan p, double delta);
 
 /* One-cavity FFT plan: k = 0 the size's default shape (the one batches use);
- * k = 1, for N = 256, 1024 and 2048 in the FP32 forms, a shape with 8 points
- * per lane and more lanes per line (256: 32 lanes x 8 lines, radices 8 8 4;
- * 1024: 128 lanes x 4 lines, 8 8 4 4; 2048: 256 lanes x 4 lines, 8 8 8 4),
- * whose shorter per-lane instruction chain suits a lone cavity, which keeps
- * at most one workgroup per CU busy.  Every plan computes the same transform
+ * k = 1, for N = 256 in the FP32 forms, a shape with 8 points per lane and
+ * twice the lanes per line (32 lanes x 8 lines, radices 8 8 4), whose shorter
+ * per-lane instruction chain suits a lone small cavity.  Every plan computes the same transform
  * (results differ only by FP32 rounding); the twiddle table is rebuilt in
  * FP64 for the shape.  lsr_autotune(p, NULL, path) times the plans of the
  * size and keeps the fastest.  Waits for the plan's stream.  LSR_EUNSUPPORTED

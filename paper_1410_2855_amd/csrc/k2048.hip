@@ -1,9 +1,7 @@
-// Kernels for N = 2048 (FP32 and FP64 forms, and the one-cavity shape with
-// 8 points per lane).
+// Kernels for N = 2048 (FP32 and FP64 forms).
 #include "kernels_impl.hpp"
 
 namespace lsr {
 const Launchers* launchers_2048f() { return make_launchers<S2048, float>(); }
 const Launchers* launchers_2048d() { return make_launchers<D2048, double>(); }
-const Launchers* launchers_2048l() { return make_launchers<L2048, float>(); }
 }  // namespace lsr

@@ -247,8 +247,8 @@ __device__ __forceinline__ void finalize_sums(const CavDesc& d) {
 // ---------------------------------------------------------------------------
 // Local step, inversion update and diagnostics sums on the lane's points of
 // row y (register order of the first forward radix = natural x order), in
-// chunks of four points: the aperture power of a chunk runs as one loop
-// uniform across lanes.
+// chunks of points: the aperture power of a chunk runs as one loop uniform
+// across lanes.
 // MODEL is the local-step code: its low bits select the local step (0 B class
 // with the Euler update, 1 B class with the update exact over a trip, 2 class
 // A), MODEL_ROUGH adds the roughness factor.  A compile-time choice, so the
@@ -279,8 +279,11 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
     const int h = kind == AP_SUPERGAUSS ? d.ap_half_order : 1;
     // the lane's points in chunks of CH: the aperture of a chunk is computed
     // right before its points are used, so only CH aperture values and
-    // radii are live at a time
-    constexpr int CH = 4;
+    // radii are live at a time.  The 4096-point row kernels run at the
+    // register limit of 16 waves per CU, and chunks of 4 free 12 registers
+    // there (spill 48 -> 28 bytes per lane); the other shapes compute all
+    // their points in one chunk (smaller chunks measured 4% slower at 1024).
+    constexpr int CH = S::N >= 4096 ? 4 : P;
     static_assert(P % CH == 0, "points per lane must be a multiple of the chunk");
     sfor<0, P / CH>([&](auto cc) {
         constexpr int c0 = decltype(cc)::value * CH;

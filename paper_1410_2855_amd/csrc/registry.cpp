@@ -7,15 +7,11 @@ namespace lsr {
 LSR_DECL(256) LSR_DECL(384) LSR_DECL(512) LSR_DECL(768) LSR_DECL(1024) LSR_DECL(2048) LSR_DECL(4096)
 #undef LSR_DECL
 const Launchers* launchers_256l();
-const Launchers* launchers_1024l();
-const Launchers* launchers_2048l();
 
 const Launchers* launchers_alt(int N, int k) {
     if (k != 1) return nullptr;
     switch (N) {
     case 256:  return launchers_256l();
-    case 1024: return launchers_1024l();
-    case 2048: return launchers_2048l();
     default:   return nullptr;
     }
 }

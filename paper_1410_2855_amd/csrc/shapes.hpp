@@ -111,13 +111,15 @@ using S2048r = Shape<2048, 128, 4, 16, 16, 8>;
 // same 4 x 4 tiles and LDS, two waves per SIMD with the registers to hold
 // every value without spilling.
 using S4096w = Shape<4096, 128, 4, 16, 16, 16>;
-// One-cavity plans of 256, 1024 and 2048 can take a shape with 8 points per
-// lane instead of 12-16 (lsr_plan_set_fft_plan): a lone cavity keeps at most
-// one workgroup per CU busy, so its passes are bound by the chain of
-// dependent instructions of a lane, which fewer points per lane shorten.
+// A one-cavity plan of 256 can take a shape with 8 points per lane instead
+// of 16 (lsr_plan_set_fft_plan): a lone small cavity keeps few workgroups
+// busy, so its passes are bound by the chain of dependent instructions of a
+// lane, which fewer points per lane shorten (15.7 -> 11.8 us per trip).
+// Shapes of 8 points per lane for 1024 (128 lanes, radices 8 8 4 4) and
+// 2048 (256 lanes, 8 8 8 4) measured slower than the defaults (22.3 ->
+// 24.3 and 44.5 -> 57.2 us): their lines span several waves, so every
+// exchange becomes a workgroup barrier.
 using L256  = Shape<256, 32, 8, 8, 8, 4>;
-using L1024 = Shape<1024, 128, 4, 8, 8, 4, 4>;
-using L2048 = Shape<2048, 256, 4, 8, 8, 8, 4>;
 // FP64 complex field (16 B/point): half the lines per workgroup.
 using D256  = Shape<256, 16, 8, 16, 16>;
 using D384  = Shape<384, 16, 8, 8, 12, 4>;
@@ -131,7 +133,7 @@ static_assert(S256::valid() && S384::valid() && S512::valid() && S768::valid() &
               S1024::valid() && S2048::valid() && S4096::valid(), "bad fp32 shape");
 static_assert(S512r::valid() && S1024r::valid() && S1024t::valid() && S2048r::valid() && S4096w::valid(),
               "bad alternative shape");
-static_assert(L256::valid() && L1024::valid() && L2048::valid(), "bad one-cavity shape");
+static_assert(L256::valid(), "bad one-cavity shape");
 static_assert(D256::valid() && D384::valid() && D512::valid() && D768::valid() &&
               D1024::valid() && D2048::valid() && D4096::valid(), "bad fp64 shape");
 
