@@ -445,7 +445,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--reps", type=int, default=5,
+    ap.add_argument("--reps", type=int, default=7,
                     help="timed calls of --steps round trips each; the reported time is their median")
     ap.add_argument("--cavities", type=int, default=64, help="cavities of the 1024^2 workload")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="sweep1024",
