@@ -364,7 +364,9 @@ int lsr_batch_test_wait(lsr_batch b, int extra_need, int spin_limit);
  * launches whose resident workgroups prefetch their next task's data while
  * computing the current one (groups of a single grid size; other groups fall
  * back to 1).  variant:
- * register-budget variant of the kernels (0 = 2 waves/SIMD, 1 = 3).
+ * register budget of the kernels: 0 = four waves per SIMD (128 VGPRs; a
+ * kernel that needs more spills a few registers), 1 = two waves per SIMD
+ * (256); 4096 and the mixed-size kernels have one budget.
  * wgs_per_cu: resident workgroups per CU of the persistent kernel (0 =
  * occupancy limit).  chunk: tickets taken per queue access.  lag: packer lag
  * in row tasks.  graph_k: trips per captured graph (0 = eager).  merge:

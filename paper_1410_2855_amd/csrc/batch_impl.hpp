@@ -82,8 +82,11 @@ __device__ __forceinline__ bool run_if(const CavDesc& d, int kind, int blk, unsi
     return true;
 }
 
-// WPE: waves per SIMD the register allocation must allow (2 leaves 256
-// VGPRs, 3 leaves 168); the autotuner picks the faster variant.
+// WPE: waves per SIMD the register allocation must allow (4 leaves 128
+// VGPRs, 2 leaves 256); the autotuner picks the faster variant.  The row
+// kernels of 256..2048 need a few registers above 128: held to 128 they
+// spill one to three words per lane and keep four waves per SIMD, which
+// measured 4% faster than three waves without a spill.
 template <int MODE, int THREADS, int LDS_BYTES, int WPE, int ANY, class... Ss>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_trip(const CavDesc* __restrict__ descs,
                                                   const int4* __restrict__ tasks, int ntasks,

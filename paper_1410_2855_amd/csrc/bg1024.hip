@@ -4,6 +4,6 @@
 
 namespace lsr {
 GroupInfo group_1024() {
-    return group_info<S1024>({GroupKernels<2, S1024>::variant(), GroupKernels<3, S1024>::variant()});
+    return group_info<S1024>({GroupKernels<4, S1024>::variant(), GroupKernels<2, S1024>::variant()});
 }
 }  // namespace lsr

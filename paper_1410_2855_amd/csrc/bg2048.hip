@@ -4,6 +4,6 @@
 
 namespace lsr {
 GroupInfo group_2048() {
-    return group_info<S2048>({GroupKernels<2, S2048>::variant(), GroupKernels<3, S2048>::variant()});
+    return group_info<S2048>({GroupKernels<4, S2048>::variant(), GroupKernels<2, S2048>::variant()});
 }
 }  // namespace lsr

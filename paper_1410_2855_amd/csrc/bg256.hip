@@ -4,6 +4,6 @@
 
 namespace lsr {
 GroupInfo group_256() {
-    return group_info<S256>({GroupKernels<2, S256>::variant(), GroupKernels<3, S256>::variant()});
+    return group_info<S256>({GroupKernels<4, S256>::variant(), GroupKernels<2, S256>::variant()});
 }
 }  // namespace lsr

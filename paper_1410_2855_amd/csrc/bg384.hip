@@ -4,6 +4,6 @@
 
 namespace lsr {
 GroupInfo group_384() {
-    return group_info<S384>({GroupKernels<2, S384>::variant(), GroupKernels<3, S384>::variant()});
+    return group_info<S384>({GroupKernels<4, S384>::variant(), GroupKernels<2, S384>::variant()});
 }
 }  // namespace lsr

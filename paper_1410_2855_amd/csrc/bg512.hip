@@ -4,6 +4,6 @@
 
 namespace lsr {
 GroupInfo group_512() {
-    return group_info<S512>({GroupKernels<2, S512>::variant(), GroupKernels<3, S512>::variant()});
+    return group_info<S512>({GroupKernels<4, S512>::variant(), GroupKernels<2, S512>::variant()});
 }
 }  // namespace lsr

@@ -4,6 +4,6 @@
 
 namespace lsr {
 GroupInfo group_768() {
-    return group_info<S768>({GroupKernels<2, S768>::variant(), GroupKernels<3, S768>::variant()});
+    return group_info<S768>({GroupKernels<4, S768>::variant(), GroupKernels<2, S768>::variant()});
 }
 }  // namespace lsr

@@ -5,7 +5,7 @@
 
 namespace lsr {
 GroupInfo group_1024r() {
-    return group_info<S1024r>({GroupKernels<2, S1024r>::variant(), GroupKernels<4, S1024r>::variant()}, 1);
+    return group_info<S1024r>({GroupKernels<4, S1024r>::variant(), GroupKernels<2, S1024r>::variant()}, 1);
 }
 GroupInfo group_1024t() { return group_info<S1024t>({GroupKernels<4, S1024t>::variant()}, 2); }
 }  // namespace lsr

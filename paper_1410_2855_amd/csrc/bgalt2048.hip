@@ -4,6 +4,6 @@
 
 namespace lsr {
 GroupInfo group_2048r() {
-    return group_info<S2048r>({GroupKernels<2, S2048r>::variant(), GroupKernels<4, S2048r>::variant()}, 1);
+    return group_info<S2048r>({GroupKernels<4, S2048r>::variant(), GroupKernels<2, S2048r>::variant()}, 1);
 }
 }  // namespace lsr

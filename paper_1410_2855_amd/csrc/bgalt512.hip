@@ -4,6 +4,6 @@
 
 namespace lsr {
 GroupInfo group_512r() {
-    return group_info<S512r>({GroupKernels<2, S512r>::variant(), GroupKernels<4, S512r>::variant()}, 1);
+    return group_info<S512r>({GroupKernels<4, S512r>::variant(), GroupKernels<2, S512r>::variant()}, 1);
 }
 }  // namespace lsr

@@ -4,6 +4,6 @@
 #include "batch_impl.hpp"
 
 namespace lsr {
-GroupInfo group_fix1_384() { return group_info<S384>({GroupKernelsT<2, ANY_FIXED + 1, S384>::variant(), GroupKernelsT<3, ANY_FIXED + 1, S384>::variant()}, 0, ANY_FIXED + 1); }
-GroupInfo group_fix2_384() { return group_info<S384>({GroupKernelsT<2, ANY_FIXED + 2, S384>::variant(), GroupKernelsT<3, ANY_FIXED + 2, S384>::variant()}, 0, ANY_FIXED + 2); }
+GroupInfo group_fix1_384() { return group_info<S384>({GroupKernelsT<4, ANY_FIXED + 1, S384>::variant(), GroupKernelsT<2, ANY_FIXED + 1, S384>::variant()}, 0, ANY_FIXED + 1); }
+GroupInfo group_fix2_384() { return group_info<S384>({GroupKernelsT<4, ANY_FIXED + 2, S384>::variant(), GroupKernelsT<2, ANY_FIXED + 2, S384>::variant()}, 0, ANY_FIXED + 2); }
 }  // namespace lsr

@@ -1,6 +1,7 @@
 // desc.hpp -- per-cavity descriptor read by the kernels (host and device).
 #pragma once
 
+#include <cmath>
 #include <cstdint>
 
 namespace lsr {
@@ -63,9 +64,23 @@ struct CavDesc {
     double sqrtR;
     double N0, inv_T1, mod_amp;
     double dx;
-    double inv_r0sq;        // 1/r0^2 (super-Gaussian), 1/(2 r0^2) (Gaussian)
+    double ap_step;         // grid step in aperture units: with X' = (x - N/2) ap_step and
+                            // Y' likewise, u = X'^2 + Y'^2 and A = 2^(-u^h) (aperture_step)
     double phase_c;         // PLAIN: pi lambda L / (N dx)^2, rad per index^2
     double inv_nn;          // 1/N^2
 };
+
+// The aperture amplitude A = exp(-(r^2/r0^2)^h) (super-Gaussian of order 2h)
+// or exp(-r^2/(2 r0^2)) (Gaussian, h = 1) written as A = 2^(-u^h) with
+// u = c r^2, c = log2(e)^(1/h) / r0^2 (resp. log2(e) / (2 r0^2)): the base-2
+// exponential and the scale by log2(e) then cost nothing per point, and the
+// grid step is scaled by sqrt(c) so that u = X'^2 + Y'^2.  0 without a
+// smooth aperture.
+inline double aperture_step(int kind, double radius, int half_order, double dx) {
+    const double log2e = 1.4426950408889634073599246810019;
+    if (kind == AP_SUPERGAUSS) return dx * std::sqrt(std::pow(log2e, 1.0 / half_order) / (radius * radius));
+    if (kind == AP_GAUSS) return dx * std::sqrt(log2e / (2.0 * radius * radius));
+    return 0.0;
+}
 
 }  // namespace lsr

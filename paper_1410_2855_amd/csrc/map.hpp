@@ -53,6 +53,11 @@ __device__ __forceinline__ typename V16<T>::type pack16(const cx<T>* e) {
 // factors, whose arguments are O(1) where the factors matter.
 __device__ __forceinline__ float ex(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896340736f); }
 __device__ __forceinline__ double ex(double x) { return exp(x); }
+// 2^x: v_exp_f32 for FP32, the library exp2 for FP64
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ double ex2(double x) { return exp2(x); }
+// log2(e) / 2: exp(n/2) = 2^(n log2(e)/2), one multiply
+template <typename T> constexpr T HALF_LOG2E = (T)0.72134752044448170367996234050095;
 __device__ __forceinline__ void sc(float x, float* s, float* c) { sincosf(x, s, c); }
 __device__ __forceinline__ void sc(double x, double* s, double* c) { sincos(x, s, c); }
 
@@ -269,20 +274,23 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
     constexpr int P = S::P;
     constexpr int LS = MODEL & MODEL_MASK;
     constexpr bool ROUGH = (MODEL & MODEL_ROUGH) != 0;
-    const T dx = (T)d.dx;
     const T half = (T)(0.5 * S::N);
-    const T Y = ((T)y - half) * dx;
-    const T Y2 = Y * Y;
-    const T sqR = (T)d.sqrtR, N0 = (T)d.N0, iT1 = (T)d.inv_T1, mamp = (T)d.mod_amp;
-    const T ir = (T)d.inv_r0sq;
+    const T sqR = (T)d.sqrtR, N0 = (T)d.N0, iT1 = (T)d.inv_T1;
     const int kind = d.ap_kind;
     const T* pc = static_cast<const T*>(d.pump_c);
     const cx<T>* foc = static_cast<const cx<T>*>(d.foc);
     const void* rough = d.rough;
     // byte offsets of row y from the cavity's (uniform) array bases
     const unsigned row = (unsigned)y * (unsigned)S::N * (unsigned)sizeof(T);
+    // aperture coordinates in units where u = X'^2 + Y'^2 and A = 2^(-u^h);
+    // a point's X' is the lane's base plus a compile-time multiple of the step
+    const T st = (T)d.ap_step;
+    const T Yp = ((T)y - half) * st;
+    const T Y2 = Yp * Yp;
+    const T Xl = ((T)lane - half) * st;
 
-    const T pcy = pc ? pc[y] : (T)0;
+    // modulated pump N0 (1 + m c(x) c(y)) = N0 + (N0 m c(y)) c(x)
+    const T pmy = pc ? (T)(d.N0 * d.mod_amp) * pc[y] : (T)0;
     const cx<T> fy = foc ? foc[y] : cx<T>{(T)1, (T)0};
     const int h = kind == AP_SUPERGAUSS ? d.ap_half_order : 1;
     // the lane's points in chunks of CH: the aperture of a chunk is computed
@@ -306,20 +314,23 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
         } else if (kind == AP_NONE) {
             sfor<0, CH>([&](auto jc) { A[decltype(jc)::value] = (T)1; });
         } else {
-            // u = r^2/r0^2 (super-Gaussian) or r^2/(2 r0^2) (Gaussian); exponent
-            // u^h, h = order/2, by squaring (a loop uniform across lanes)
+            // u = c r^2 (see aperture_step), then u^h by binary powering in
+            // loops uniform across lanes (u^5: three multiplies), A = 2^(-u^h)
             T u[CH];
             sfor<0, CH>([&](auto jc) {
                 constexpr int j = decltype(jc)::value, i = c0 + j;
-                const T X = ((T)reg_pos<S, R>(lane, i / R, i % R) - half) * dx;
-                u[j] = fma_(X, X, Y2) * ir;
-                A[j] = (T)1;
+                constexpr int off = (i / R) * S::L + (i % R) * (S::N / R);   // reg_pos less the lane
+                const T X = fma_((T)off, st, Xl);
+                u[j] = fma_(X, X, Y2);
             });
-            for (int e = h; e; e >>= 1) {
-                if (e & 1) sfor<0, CH>([&](auto jc) { A[decltype(jc)::value] *= u[decltype(jc)::value]; });
+            int e = h;
+            for (; !(e & 1); e >>= 1) sfor<0, CH>([&](auto jc) { u[decltype(jc)::value] *= u[decltype(jc)::value]; });
+            sfor<0, CH>([&](auto jc) { A[decltype(jc)::value] = u[decltype(jc)::value]; });
+            for (e >>= 1; e; e >>= 1) {
                 sfor<0, CH>([&](auto jc) { u[decltype(jc)::value] *= u[decltype(jc)::value]; });
+                if (e & 1) sfor<0, CH>([&](auto jc) { A[decltype(jc)::value] *= u[decltype(jc)::value]; });
             }
-            sfor<0, CH>([&](auto jc) { A[decltype(jc)::value] = ex(-A[decltype(jc)::value]); });
+            sfor<0, CH>([&](auto jc) { A[decltype(jc)::value] = ex2(-A[decltype(jc)::value]); });
         }
         sfor<0, CH>([&](auto jc) {
             constexpr int j = decltype(jc)::value, i = c0 + j;
@@ -331,8 +342,8 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
             // amplitude gain of the sheet: frozen inversion exp(N/2) (B class),
             // or the class-A saturable gain exp(N / (2 (1 + T1 I)))
             T eh;
-            if constexpr (LS == 2) eh = ex((T)0.5 * n * iT1 / (iT1 + I));
-            else eh = ex((T)0.5 * n);
+            if constexpr (LS == 2) eh = ex2(HALF_LOG2E<T> * n * iT1 / (iT1 + I));
+            else eh = ex2(HALF_LOG2E<T> * n);
             const T A2 = A[j] * A[j];
             const T aeh = A[j] * eh;
             // bookkeeping in FP64 from the first term: a product of two
@@ -351,7 +362,7 @@ __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc&
             if constexpr (ROUGH) g = cmul(g, gld<cx<T>>(rough, 2u * row + (unsigned)sizeof(cx<T>) * x));
             v[i] = g;
             if constexpr (MODE != ROW_DIAG) {
-                const T pump = pc ? N0 * fma_(mamp * gld<T>(pc, (unsigned)sizeof(T) * x), pcy, (T)1) : N0;
+                const T pump = pc ? fma_(gld<T>(pc, (unsigned)sizeof(T) * x), pmy, N0) : N0;
                 T nn;
                 if constexpr (LS == 0) {
                     // forward Euler over one trip
@@ -383,7 +394,7 @@ struct RowRegs {
 
 template <class S, typename T, int MODE>
 __device__ __forceinline__ void row_load(const CavDesc& d, int rb, RowRegs<S, T>& in) {
-    const int tid = opaque_tid<false>();
+    const int tid = opaque_tid<true>();
     const int line = tid / S::L, lane = tid % S::L;
     const int y = rb * S::LPW + line;
     constexpr int RF = R_FIRST<S>;
@@ -404,7 +415,7 @@ __device__ __forceinline__ void row_load(const CavDesc& d, int rb, RowRegs<S, T>
 template <class S, typename T, int MODE, int TWS = TW_GLOBAL, int MODEL = 0, class Prefetch>
 __device__ __forceinline__ void row_body(const CavDesc& d, int rb, cx<T>* lds, double* red, RowRegs<S, T>& in,
                                          Prefetch&& prefetch, const cx<T>* ltw = nullptr) {
-    const int tid = opaque_tid<false>();
+    const int tid = opaque_tid<true>();
     const int line = tid / S::L, lane = tid % S::L;
     const int y = rb * S::LPW + line;
     cx<T>* blk = static_cast<cx<T>*>(d.E) + (size_t)rb * S::LPW * S::N;

@@ -220,7 +220,7 @@ extern "C" int lsr_roundtrips_static(int N, double dx, double lambda, double L, 
     d.inv_T1 = 1.0 / T1;
     d.mod_amp = modulated ? mod_amp : 0.0;
     d.dx = dx;
-    d.inv_r0sq = a.kind == 1 ? 1.0 / (a.radius * a.radius) : a.kind == 2 ? 1.0 / (2.0 * a.radius * a.radius) : 0.0;
+    d.ap_step = aperture_step(a.kind, a.radius, d.ap_half_order, dx);
     d.phase_c = kTwoPiD * 0.5 * lambda * L / ((N * dx) * (N * dx));
     d.inv_nn = 1.0 / ((double)N * (double)N);
 

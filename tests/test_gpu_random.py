@@ -67,3 +67,48 @@ def test_random_cavity_matches_oracle(i):
     assert rel(e.cpu().numpy(), eo) <= tol, case
     assert rel(n.cpu().numpy(), no) <= tol, case
     assert rel(tr, to) <= max(tol, cav.N ** 2 * 2.3e-16), case
+
+
+BATCH_CASES = 6
+
+
+@pytest.mark.parametrize("i", range(BATCH_CASES))
+def test_random_batch_is_bitwise_the_one_cavity_path(i):
+    """Batches of randomly drawn cavities (the draws above with sizes up to
+    2048, one sheet count per batch, the FP64-table form batches take), on a
+    random engine and graph length, in calls of random lengths: every
+    cavity bitwise the one-cavity path over the same trips."""
+    r = np.random.default_rng(7000 + i)
+    m = int(r.choice([1, 1, 2, 3]))
+    cavs = []
+    for k in range(int(r.integers(3, 7))):
+        cav, _, _ = draw(100 * i + k)
+        cavs.append(cav.with_(slices=m, N=int(r.choice([256, 384, 512, 768, 1024, 2048])), index=300 + k))
+    engine = int(r.choice([0, 1, 1, 2]))
+    graph_k = int(r.choice([0, 2, 5, 16]))
+    calls = [int(x) for x in r.integers(1, 9, size=3)]
+    trips = sum(calls)
+    ref = []
+    for c in cavs:
+        p = lsr.Plan(c)
+        e, n = p.state(*initial_state(c))
+        p.roundtrips(e, n, trips)
+        p.sync()
+        ref.append((e, n))
+        p.close()
+    plans = [lsr.Plan(c) for c in cavs]
+    st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+    Es, Ns = [x[0] for x in st], [x[1] for x in st]
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_configure(b, engine=engine, graph_k=graph_k)
+    for k in calls:
+        lsr.lsr_batch_roundtrips(b, Es, Ns, k)
+    for p in plans:
+        p.sync()
+    case = "sheets=%d engine=%d graph_k=%d calls=%s sizes=%s models=%s" % (
+        m, engine, graph_k, calls, [c.N for c in cavs], [c.model for c in cavs])
+    for j in range(len(cavs)):
+        assert torch.equal(Es[j], ref[j][0]) and torch.equal(Ns[j], ref[j][1]), "%s cavity %d" % (case, j)
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
