@@ -396,10 +396,15 @@ def oracle_per_size(sizes=(256, 384, 512, 768, 1024, 2048, 4096), target_s: floa
     return {"host": host, "per_size": rows}
 
 
+# (N, batch FFT plan) pairs with an alternative plan compiled
+BATCH_PLANS = {(256, 1), (512, 1), (1024, 1), (1024, 2), (2048, 1), (4096, 1)}
+
+
 def bench_single(args):
     """One cavity alone: lsr_roundtrips calls of --steps trips (one launch per
     pass, no graph), the median of --reps calls; the one-cavity FFT plan from
-    --fft-plan, or the autotuner's choice (-1)."""
+    --fft-plan, or the autotuner's choice (-1).  Also the same calls replayed
+    from graphs (a batch of one), per batch FFT plan."""
     import torch
 
     from paper_1410_2855_amd import lsr
@@ -426,6 +431,27 @@ def bench_single(args):
     t = statistics.median(per)
     row_ms, col_ms = lsr.lsr_time_kernels(p.handle, e, n, 20)
     p.sync()
+    # the same cavity replayed from HIP graphs: a batch of one, one graph per
+    # call of --steps trips, captured before the timed calls; each batch FFT
+    # plan of the size (plan 1 of 256 is the one-cavity plan 1)
+    graph = {}
+    for shape in (0, 1, 2):
+        b = lsr.lsr_batch_create([p.handle])
+        cfg = lsr.lsr_batch_configure(b, engine=1, graph_k=args.steps, shape=shape)
+        if cfg["shape"] != shape or (shape > 0 and (cav.N, shape) not in BATCH_PLANS):
+            lsr.lsr_batch_destroy(b)
+            continue
+        lsr.lsr_batch_prepare(b, args.steps)
+        lsr.lsr_batch_roundtrips(b, [e], [n], args.steps)
+        torch.cuda.synchronize()
+        g = []
+        for _ in range(args.reps):
+            t0 = time.perf_counter()
+            lsr.lsr_batch_roundtrips(b, [e], [n], args.steps)
+            torch.cuda.synchronize()
+            g.append((time.perf_counter() - t0) / args.steps)
+        lsr.lsr_batch_destroy(b)
+        graph["plan%d" % shape] = round(statistics.median(g) * 1e6, 2)
     p.close()
     pts = cav.N * cav.N
     out = {"metric": "grid-pts x round-trips/s, one cavity", "value": pts / t, "unit": "grid-pts*round-trips/s",
@@ -436,6 +462,7 @@ def bench_single(args):
                       "fft_plan": args.fft_plan if args.fft_plan >= 0 else "autotuned"},
            "timing": {"reps": len(per), "statistic": "median", "ms_per_step_each": [round(x * 1e3, 5) for x in per]},
            "kernels_ms": {"row_pass": round(row_ms, 5), "column_pass": round(col_ms, 5)},
+           "graph_us_per_trip": graph,
            "hbm_frac_whole_step": round(pts * TRIP_BYTES_PER_PT / t / 1e9 / HBM_PEAK_GBS, 4)}
     print(json.dumps(out), flush=True)
 

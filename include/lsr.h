@@ -378,6 +378,7 @@ int lsr_batch_test_wait(lsr_batch b, int extra_need, int spin_limit);
  * have one compiled (others keep their default):
  *   1  reversed radix order: 512 as 16 8 4, 1024 as 16 16 4, 2048 as 16 16 8;
  *      4096 with 128 lanes per line (32 points per lane, 512 threads);
+ *      256 with 8 points per lane (the one-cavity FFT plan 1 of that size);
  *   2  1024 on 8 x 8 tiles, eight lines per workgroup.
  * Every plan computes the same transform; with an alternative plan the
  * batch's results differ from the one-cavity path's only by rounding (they

@@ -28,6 +28,7 @@ GroupInfo group_1024r();
 GroupInfo group_1024t();
 GroupInfo group_2048r();
 GroupInfo group_4096w();
+GroupInfo group_256l();
 GroupInfo group_any_256();
 GroupInfo group_any_384();
 GroupInfo group_any_512();
@@ -61,7 +62,7 @@ static const std::vector<GroupInfo>& groups() {
     static const std::vector<GroupInfo> g = {group_256(),  group_384(),  group_512(),
                                              group_768(),  group_1024(), group_2048(),
                                              group_4096(), group_small(), group_512r(),
-                                             group_1024r(), group_1024t(), group_2048r(), group_4096w(),
+                                             group_1024r(), group_1024t(), group_2048r(), group_4096w(), group_256l(),
                                              group_any_256(), group_any_384(), group_any_512(),
                                              group_any_768(), group_any_1024(), group_any_2048(),
                                              group_any_4096(), group_anyr_256(), group_anyr_384(),

@@ -230,7 +230,7 @@ def test_batch_follows_new_state_buffers_between_calls():
         p.close()
 
 
-@pytest.mark.parametrize("N,shape", [(512, 1), (1024, 1), (1024, 2), (2048, 1), (4096, 1)])
+@pytest.mark.parametrize("N,shape", [(256, 1), (512, 1), (1024, 1), (1024, 2), (2048, 1), (4096, 1)])
 @pytest.mark.parametrize("engine", [1, 0, 2])
 def test_alternative_fft_plans(N, shape, engine):
     """The batch's alternative FFT plans (another radix order, 8 x 8 tiles, or
@@ -364,3 +364,36 @@ def test_persistent_wait_failure_flags_every_cavity():
     lsr.lsr_batch_destroy(b)
     for p in plans:
         p.close()
+
+
+@pytest.mark.parametrize("graph_k", [0, 5, 12])
+def test_batch_plan_matches_the_one_cavity_plan_of_256(graph_k):
+    """Batch FFT plan 1 of 256 is the one-cavity FFT plan 1 (8 points per
+    lane): a batch of one (and of three) on it, eager or replayed from
+    graphs, is bitwise the plan path with lsr_plan_set_fft_plan(p, 1)."""
+    cavs = [c.with_(N=256) for c in sweep(3, seed=23, sizes=(256,))]
+    trips = 11
+    ref = []
+    for c in cavs:
+        p = lsr.Plan(c)
+        lsr.lsr_plan_set_fft_plan(p.handle, 1)
+        e, n = p.state(*initial_state(c))
+        p.roundtrips(e, n, trips)
+        p.sync()
+        ref.append((e, n))
+        p.close()
+    for subset in ([0], [0, 1, 2]):
+        plans, Es, Ns = make([cavs[i] for i in subset])
+        b = lsr.lsr_batch_create([p.handle for p in plans])
+        cfg = lsr.lsr_batch_configure(b, engine=1, shape=1, graph_k=graph_k)
+        assert cfg["shape"] == 1
+        if graph_k:
+            lsr.lsr_batch_prepare(b, trips)
+        lsr.lsr_batch_roundtrips(b, Es, Ns, trips)
+        for p in plans:
+            p.sync()
+        for j, i in enumerate(subset):
+            assert torch.equal(Es[j], ref[i][0]) and torch.equal(Ns[j], ref[i][1]), (subset, i)
+        lsr.lsr_batch_destroy(b)
+        for p in plans:
+            p.close()
