@@ -164,9 +164,11 @@ int lsr_propagate(lsr_plan p, const void* E_in, double z, void* E_out);
 int lsr_plan_set_filter(lsr_plan p, double delta);
 
 /* One-cavity FFT plan: k = 0 the size's default shape (the one batches use);
- * k = 1, for N = 256 in the FP32 forms, a shape with 8 points per lane and
- * twice the lanes per line (32 lanes x 8 lines, radices 8 8 4), whose shorter
- * per-lane instruction chain suits a lone small cavity.  Every plan computes the same transform
+ * for N = 256 in the FP32 forms, k = 1 a shape with 8 points per lane and
+ * twice the lanes per line (32 lanes x 8 lines, radices 8 8 4), k = 2 and 3
+ * four points per lane (64 lanes, radix 4 throughout) on four and two lines
+ * per workgroup; their shorter per-lane instruction chains suit a lone small
+ * cavity.  Every plan computes the same transform
  * (results differ only by FP32 rounding); the twiddle table is rebuilt in
  * FP64 for the shape.  lsr_autotune(p, NULL, path) times the plans of the
  * size and keeps the fastest.  Waits for the plan's stream.  LSR_EUNSUPPORTED

@@ -903,7 +903,7 @@ static int tune_plan(lsr_plan p, const char* path) {
     auto it = cache.find(key);
     if (it != cache.end()) return lsr_plan_set_fft_plan(p, it->second.shape);
     std::vector<int> cands = {0};
-    for (int k = 1; k <= 1; ++k)
+    for (int k = 1; k <= 3; ++k)
         if (p->prec != PREC_FP64 && launchers_alt(p->N, k)) cands.push_back(k);
     DeviceGuard dg(p->device);
     LSR_HIP(hipStreamSynchronize(p->stream));

@@ -7,12 +7,16 @@ namespace lsr {
 LSR_DECL(256) LSR_DECL(384) LSR_DECL(512) LSR_DECL(768) LSR_DECL(1024) LSR_DECL(2048) LSR_DECL(4096)
 #undef LSR_DECL
 const Launchers* launchers_256l();
+const Launchers* launchers_256q();
+const Launchers* launchers_256p();
 
 const Launchers* launchers_alt(int N, int k) {
-    if (k != 1) return nullptr;
-    switch (N) {
-    case 256:  return launchers_256l();
-    default:   return nullptr;
+    if (N != 256) return nullptr;
+    switch (k) {
+    case 1:  return launchers_256l();
+    case 2:  return launchers_256q();
+    case 3:  return launchers_256p();
+    default: return nullptr;
     }
 }
 

@@ -258,19 +258,20 @@ def test_bad_arguments_on_device():
     p.close()
 
 
-@pytest.mark.parametrize("N", [256])
-def test_one_cavity_fft_plan_with_eight_points_per_lane(N, tmp_path):
-    """The one-cavity FFT plan with 8 points per lane computes the same map:
-    50 trips against the oracle at the usual bar, 3 trips against the default
-    plan to FP32 rounding; a batch holding such a plan runs its own plan and
-    stays bitwise the default one-cavity path; the autotuner picks one of the
-    two and records it; FP64 plans and other sizes have none."""
+@pytest.mark.parametrize("N,k", [(256, 1), (256, 2), (256, 3)])
+def test_one_cavity_fft_plans_of_256(N, k, tmp_path):
+    """The one-cavity FFT plans of 256 (8 points per lane; 4 points per lane
+    on four or two lines per workgroup) compute the same map: 50 trips
+    against the oracle at the usual bar, 3 trips against the default plan to
+    FP32 rounding; a batch holding such a plan runs its group's plan and
+    stays bitwise the default one-cavity path; the autotuner picks one of
+    them and records it; FP64 plans and other sizes have none."""
     from paper_1410_2855_amd.inputs import Cavity
 
     cav = Cavity(N=N, F=200.0 if N < 2048 else 1000.0, R=0.9, pump_ratio=2.5, T1=600.0, index=9)
     e0, n0 = initial_state(cav)
     p = lsr.Plan(cav)
-    lsr.lsr_plan_set_fft_plan(p.handle, 1)
+    lsr.lsr_plan_set_fft_plan(p.handle, k)
     trips = 50 if N < 2048 else 20
     e, n = p.state(e0, n0)
     p.roundtrips(e, n, trips)
@@ -295,15 +296,20 @@ def test_one_cavity_fft_plan_with_eight_points_per_lane(N, tmp_path):
     cache = str(tmp_path / "tune.json")
     lsr.lsr_autotune(q.handle, None, cache)
     import json
-    assert json.load(open(cache))["gfx950:plan:%d:1" % N]["shape"] in (0, 1)
+    assert json.load(open(cache))["gfx950:plan:%d:1" % N]["shape"] in (0, 1, 2, 3)
     f = lsr.Plan(cav, prec=lsr.LSR_PREC_FP64)
     with pytest.raises(lsr.LsrError) as ei:
-        lsr.lsr_plan_set_fft_plan(f.handle, 1)
+        lsr.lsr_plan_set_fft_plan(f.handle, k)
     assert ei.value.code == lsr.LSR_EUNSUPPORTED
     for x in (p, q, f):
         x.close()
     r = lsr.Plan(cav.with_(N=512))
     with pytest.raises(lsr.LsrError) as ei:
-        lsr.lsr_plan_set_fft_plan(r.handle, 1)
+        lsr.lsr_plan_set_fft_plan(r.handle, k)
+    assert ei.value.code == lsr.LSR_EUNSUPPORTED
+    r.close()
+    r = lsr.Plan(cav)
+    with pytest.raises(lsr.LsrError) as ei:
+        lsr.lsr_plan_set_fft_plan(r.handle, 4)
     assert ei.value.code == lsr.LSR_EUNSUPPORTED
     r.close()
