@@ -567,8 +567,8 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
             const bool runs = lvl >= ANY_FIXED ? d.model == lvl - ANY_FIXED
                             : lvl == 2 ? true : lvl == 1 ? (d.model & MODEL_ROUGH) == 0 : d.model == 0;
             if (!runs) return set_err(LSR_EINVAL, "cavity %d: local-step code %d not in its group", c, d.model);
-            for (int k = 0; k < g.g->nsizes; ++k)
-                if (g.g->sizes[k] == d.N) d.tw = g.d_tw[k];
+            for (int z = 0; z < g.g->nsizes; ++z)
+                if (g.g->sizes[z] == d.N) d.tw = g.d_tw[z];
             d.nrb = group_blocks(g, d.N);
             h.push_back(d);
         }

@@ -56,6 +56,35 @@ __device__ __forceinline__ cx<T> twc(cx<T> a) {
     }
 }
 
+// For a twiddle exp(DIR 2 pi i M / R) of the form (+-1 +- i)/sqrt(2): the
+// sign of its real part (twc scales the rotated value by that sign times
+// 1/sqrt(2)); 0 for every other twiddle.
+template <int R, int M, int DIR>
+constexpr int half_sqrt2_sign() {
+    constexpr int m = ((M % R) + R) % R;
+    if constexpr (8 * m == R || 8 * m == 3 * R || 8 * m == 5 * R || 8 * m == 7 * R)
+        return ce_cos(2.0 * kPi * m / R) > 0 ? 1 : -1;
+    else
+        return 0;
+}
+
+// twc for a (+-1 +- i)/sqrt(2) twiddle without its scale: the caller folds
+// (sign) / sqrt(2) into the multiply-adds that consume the value.
+template <int R, int M, int DIR, typename T>
+__device__ __forceinline__ cx<T> twc_unscaled(cx<T> a) {
+    constexpr int m = ((M % R) + R) % R;
+    constexpr double th = 2.0 * kPi * m / R;
+    constexpr bool same = (ce_cos(th) > 0) == (DIR * ce_sin(th) > 0);
+    if constexpr (same) return {a.re - a.im, a.re + a.im};   // c == s
+    else return {a.re + a.im, a.im - a.re};                  // c == -s
+}
+
+// a + c b, componentwise, as fused multiply-adds.
+template <typename T>
+__device__ __forceinline__ cx<T> fma_cx(cx<T> b, T c, cx<T> a) {
+    return {fma_(b.re, c, a.re), fma_(b.im, c, a.im)};
+}
+
 // In-place DFT of length R in registers: X_k = sum_n x_n exp(DIR 2 pi i nk/R).
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft(cx<T>* x) {
@@ -85,6 +114,9 @@ __device__ __forceinline__ void dft(cx<T>* x) {
         // then B DFTs of length A; X[k2 + B k1].
         constexpr int A = (R % 4 == 0) ? 4 : ((R % 3 == 0) ? 3 : 2);
         constexpr int B = R / A;
+        // with A = 4 the (+-1 +- i)/sqrt(2) twiddles stay unscaled and their
+        // scale is folded into the length-4 DFTs as fused multiply-adds
+        constexpr bool FOLD = A == 4;
         cx<T> y[R];
         sfor<0, A>([&](auto n1c) {
             constexpr int n1 = decltype(n1c)::value;
@@ -93,15 +125,63 @@ __device__ __forceinline__ void dft(cx<T>* x) {
             dft<B, DIR>(s);
             sfor<0, B>([&](auto kc) {
                 constexpr int k2 = decltype(kc)::value;
-                y[n1 * B + k2] = twc<R, n1 * k2, DIR>(s[k2]);
+                if constexpr (FOLD && half_sqrt2_sign<R, n1 * k2, DIR>() != 0)
+                    y[n1 * B + k2] = twc_unscaled<R, n1 * k2, DIR>(s[k2]);
+                else
+                    y[n1 * B + k2] = twc<R, n1 * k2, DIR>(s[k2]);
             });
         });
         sfor<0, B>([&](auto kc) {
             constexpr int k2 = decltype(kc)::value;
-            cx<T> s[A];
-            sfor<0, A>([&](auto n1c) { s[decltype(n1c)::value] = y[decltype(n1c)::value * B + k2]; });
-            dft<A, DIR>(s);
-            sfor<0, A>([&](auto k1c) { x[k2 + B * decltype(k1c)::value] = s[decltype(k1c)::value]; });
+            if constexpr (FOLD) {
+                constexpr T h = (T)0.70710678118654752440084436210484904;
+                constexpr int g1 = half_sqrt2_sign<R, k2, DIR>();
+                constexpr int g2 = half_sqrt2_sign<R, 2 * k2, DIR>();
+                constexpr int g3 = half_sqrt2_sign<R, 3 * k2, DIR>();
+                const cx<T> s0 = y[k2], s1 = y[B + k2], s2 = y[2 * B + k2], s3 = y[3 * B + k2];
+                // t0, t1 = s0 +- g2 h s2
+                cx<T> t0, t1;
+                if constexpr (g2 != 0) {
+                    t0 = fma_cx(s2, (T)g2 * h, s0);
+                    t1 = fma_cx(s2, -(T)g2 * h, s0);
+                } else {
+                    t0 = s0 + s2;
+                    t1 = s0 - s2;
+                }
+                // t2 = g1 h s1 + g3 h s3, t3 = rot(g1 h s1 - g3 h s3)
+                if constexpr (g1 != 0 && g3 != 0) {
+                    // common factor c = g1 h kept out: t2 = c u, t3 = c rot(v)
+                    constexpr T c = (T)g1 * h;
+                    const cx<T> u = g1 == g3 ? s1 + s3 : s1 - s3;
+                    const cx<T> v = rot_q<DIR>(g1 == g3 ? s1 - s3 : s1 + s3);
+                    x[k2] = fma_cx(u, c, t0);
+                    x[k2 + 2 * B] = fma_cx(u, -c, t0);
+                    x[k2 + B] = fma_cx(v, c, t1);
+                    x[k2 + 3 * B] = fma_cx(v, -c, t1);
+                } else {
+                    cx<T> t2, d;
+                    if constexpr (g1 != 0) {
+                        t2 = fma_cx(s1, (T)g1 * h, s3);
+                        d = fma_cx(s1, (T)g1 * h, cx<T>{-s3.re, -s3.im});
+                    } else if constexpr (g3 != 0) {
+                        t2 = fma_cx(s3, (T)g3 * h, s1);
+                        d = fma_cx(s3, -(T)g3 * h, s1);
+                    } else {
+                        t2 = s1 + s3;
+                        d = s1 - s3;
+                    }
+                    const cx<T> t3 = rot_q<DIR>(d);
+                    x[k2] = t0 + t2;
+                    x[k2 + 2 * B] = t0 - t2;
+                    x[k2 + B] = t1 + t3;
+                    x[k2 + 3 * B] = t1 - t3;
+                }
+            } else {
+                cx<T> s[A];
+                sfor<0, A>([&](auto n1c) { s[decltype(n1c)::value] = y[decltype(n1c)::value * B + k2]; });
+                dft<A, DIR>(s);
+                sfor<0, A>([&](auto k1c) { x[k2 + B * decltype(k1c)::value] = s[decltype(k1c)::value]; });
+            }
         });
     }
 }

@@ -270,7 +270,6 @@ template <class S, typename T, int MODE, int MODEL = 0>
 __device__ __forceinline__ void local_step(cx<T>* v, const T* nv, const CavDesc& d, int y, int lane,
                                            double* acc) {
     constexpr int R = R_FIRST<S>;
-    constexpr int B = S::P / R;
     constexpr int P = S::P;
     constexpr int LS = MODEL & MODEL_MASK;
     constexpr bool ROUGH = (MODEL & MODEL_ROUGH) != 0;
