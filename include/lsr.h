@@ -316,18 +316,35 @@ void lsr_plan_destroy(lsr_plan p);
 /* local-step model, roughness and filter, and one number of gain sheets.  */
 /* ---------------------------------------------------------------------- */
 
-/* Build a batch over count >= 1 plans (borrowed).  The launch
+/* Build a batch over count >= 1 plans (borrowed: they must outlive the
+ * batch and are not copied): many independent cavities, of any mix of the
+ * supported sizes and parameters, advanced together by the map of Intro
+ * Eq. (1) with the nonlocal step of Sec. 2.2 (Eqs. (11)-(12)).  The launch
  * configuration (FFT plan, engine, register budget, grouping, task-table
  * lag, graph length k) comes from the autotune cache when it holds an entry
  * for this mix of sizes, else from built-in defaults.  The batch runs on
  * the stream its plans are bound to: every plan must be bound to the same
  * stream (LSR_EINVAL otherwise, here and in every later call that finds a
- * plan rebound to another one). */
+ * plan rebound to another one).  Errors: LSR_EINVAL for a NULL out or plan,
+ * count < 1, a plan given twice or plans on different devices;
+ * LSR_EUNSUPPORTED for plans other than the FP64TAB form, plans with
+ * different numbers of gain sheets, or a plan with a general transfer
+ * function (lsr_plan_set_transfer); LSR_ENOMEM / LSR_EDEVICE when its
+ * tables or task lists cannot be allocated or uploaded (nothing is leaked;
+ * *out is then NULL). */
 int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count);
 
-/* Advance cavity i's state (E[i], Ninv[i], laid out as for lsr_roundtrips)
- * by n_trips round trips, all cavities together, asynchronously.  The
- * per-trip sums go to each plan's trace ring. */
+/* Advance cavity i's state (E[i], Ninv[i]: device buffers laid out as for
+ * lsr_roundtrips, owned by the caller, borrowed for the call) by n_trips >= 0
+ * round trips of the map of Intro Eq. (1), all cavities together,
+ * asynchronously on the plans' stream; the results equal lsr_roundtrips on
+ * each plan bit for bit with the default FFT plans.  The per-trip sums go to
+ * each plan's trace ring.  E and Ninv hold one pointer per plan, in the
+ * order of lsr_batch_create.  Errors: LSR_EINVAL for a NULL batch, array or
+ * state pointer, a pointer not 16-byte aligned, n_trips < 0 or a plan bound
+ * to another stream; LSR_EUNSUPPORTED when a plan's number of gain sheets or
+ * nonlocal step changed to one the batch cannot run; LSR_EDEVICE when a
+ * launch fails.  A non-finite state is reported by lsr_sync of its plan. */
 int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* Ninv, int n_trips);
 
 /* Diagnostics of cavity idx of the batch; same as lsr_diag on its plan. */

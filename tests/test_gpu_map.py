@@ -279,6 +279,11 @@ def test_one_cavity_fft_plans_of_256(N, k, tmp_path):
     eo, no, to = oracle.run(oracle_params(cav), e0, n0, trips)
     assert rel(e.cpu().numpy(), eo) <= 1e-5 and rel(n.cpu().numpy(), no) <= 1e-5
     assert rel(p.trace(trips), to) <= 1e-5
+    # the diagnostics on this plan's blocks (up to 128 column blocks of partials)
+    d = p.diag(e, n)
+    radial, dom = oracle.spectrum(oracle_params(cav), e.cpu().numpy().astype(np.complex128),
+                                  n.cpu().numpy().astype(np.float64))
+    assert rel(d["radial"], radial) <= 1e-5 and d["dominant_bin"] == dom
     q = lsr.Plan(cav)
     e1, n1 = p.state(e0, n0)
     e2, n2 = q.state(e0, n0)

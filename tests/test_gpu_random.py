@@ -2,8 +2,8 @@
 oracle: grid size, Fresnel number, mirror reflectivity and curvature,
 aperture form, mirror roughness, pump level and modulation, relaxation
 time, local-step model,
-nonlocal step (Fresnel or filter), number of gain sheets and precision form,
-drawn from one seeded generator.  Each case runs a few round trips and must
+nonlocal step (Fresnel or filter), number of gain sheets, precision form and
+one-cavity FFT plan, drawn from one seeded generator.  Each case runs a few round trips and must
 match the oracle to the single-cavity bar."""
 import math
 
@@ -43,18 +43,24 @@ def draw(i):
     cav = cav.with_(model=int(r.choice([0, 0, 1, 2])), slices=int(r.choice([1, 1, 2, 3])))
     prec = int(r.choice([lsr.LSR_PREC_FP64TAB, lsr.LSR_PREC_FP64TAB, lsr.LSR_PREC_FP64]))
     trips = int(r.integers(3, 8))
-    if r.random() < 0.3:   # drawn last, so the other options of a case stay as they were
+    if r.random() < 0.3:   # drawn after the others, so their values stay as they were
         cav = cav.with_(rough_rms=float(r.uniform(0.2, 2.0)), rough_corr=int(r.integers(1, 6)))
-    return cav, prec, trips
+    # the one-cavity FFT plan (256 in the FP32 forms has four), drawn last
+    plan = int(r.integers(0, 4))
+    if N != 256 or prec == lsr.LSR_PREC_FP64:
+        plan = 0
+    return cav, prec, trips, plan
 
 
 @pytest.mark.parametrize("i", range(CASES))
 def test_random_cavity_matches_oracle(i):
-    cav, prec, trips = draw(i)
+    cav, prec, trips, plan = draw(i)
     e0, n0 = initial_state(cav)
     # a field strong enough to deplete the inversion within the run
     e0 = e0 * math.sqrt(0.3 / cav.T1) / 1e-3
     p = lsr.Plan(cav, prec=prec)
+    if plan:
+        lsr.lsr_plan_set_fft_plan(p.handle, plan)
     e, n = p.state(e0, n0)
     p.roundtrips(e, n, trips)
     p.sync()
@@ -62,8 +68,8 @@ def test_random_cavity_matches_oracle(i):
     p.close()
     eo, no, to = oracle.run(oracle_params(cav), e0, n0, trips)
     tol = 1e-11 if prec == lsr.LSR_PREC_FP64 else 5e-6
-    case = "N=%d F=%.0f model=%d sheets=%d filter=%s rough=%.2f prec=%d trips=%d" % (
-        cav.N, cav.F, cav.model, cav.slices, cav.filter_delta > 0, cav.rough_rms, prec, trips)
+    case = "N=%d F=%.0f model=%d sheets=%d filter=%s rough=%.2f prec=%d trips=%d fft plan %d" % (
+        cav.N, cav.F, cav.model, cav.slices, cav.filter_delta > 0, cav.rough_rms, prec, trips, plan)
     assert rel(e.cpu().numpy(), eo) <= tol, case
     assert rel(n.cpu().numpy(), no) <= tol, case
     assert rel(tr, to) <= max(tol, cav.N ** 2 * 2.3e-16), case
@@ -82,7 +88,7 @@ def test_random_batch_is_bitwise_the_one_cavity_path(i):
     m = int(r.choice([1, 1, 2, 3]))
     cavs = []
     for k in range(int(r.integers(3, 7))):
-        cav, _, _ = draw(100 * i + k)
+        cav = draw(100 * i + k)[0]
         cavs.append(cav.with_(slices=m, N=int(r.choice([256, 384, 512, 768, 1024, 2048])), index=300 + k))
     engine = int(r.choice([0, 1, 1, 2]))
     graph_k = int(r.choice([0, 2, 5, 16]))
