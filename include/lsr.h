@@ -168,7 +168,8 @@ int lsr_plan_set_filter(lsr_plan p, double delta);
  * twice the lanes per line (32 lanes x 8 lines, radices 8 8 4), k = 2 and 3
  * four points per lane (64 lanes, radix 4 throughout) on four and two lines
  * per workgroup; their shorter per-lane instruction chains suit a lone small
- * cavity.  Every plan computes the same transform
+ * cavity.  For N = 2048 in the FP32 forms, k = 1 a wave per line (32 points
+ * per lane), whose exchanges need no workgroup barrier.  Every plan computes the same transform
  * (results differ only by FP32 rounding); the twiddle table is rebuilt in
  * FP64 for the shape.  lsr_autotune(p, NULL, path) times the plans of the
  * size and keeps the fastest.  Waits for the plan's stream.  LSR_EUNSUPPORTED

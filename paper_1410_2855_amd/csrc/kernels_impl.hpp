@@ -7,15 +7,34 @@
 
 namespace lsr {
 
+// Waves per SIMD the register allocation of a one-cavity kernel must allow:
+// those of the workgroups a launch places on one of the 256 CUs, as far as
+// they fit in LDS (at most four waves).  A lone 2048^2 cavity launches two
+// workgroups per CU, and its row kernel, wanting 130 registers, would
+// otherwise run them one after the other (51.5 -> 43.5 us per trip); where a
+// launch brings one workgroup per CU or fewer, the compiler keeps its choice
+// (a tighter budget spills there for nothing).
+template <class S, typename T>
+constexpr int one_cavity_wpe() {
+    constexpr int lds = S::LDS_ELEMS * (int)sizeof(cx<T>) + 4 * 16 * 8;
+    constexpr int fit = 160 * 1024 / lds;
+    constexpr int per_cu = S::N / S::LPW / 256;
+    constexpr int wgs = per_cu < fit ? per_cu : fit;
+    constexpr int waves = wgs * (S::THREADS / 64) / 4;
+    return waves < 1 ? 1 : waves > 4 ? 4 : waves;
+}
+
 template <class S, typename T, int MODE, int MODEL = 0>
-__global__ __launch_bounds__(S::THREADS) void k_row(CavDesc d) {
+__global__ __launch_bounds__(S::THREADS) __attribute__((amdgpu_waves_per_eu(one_cavity_wpe<S, T>(), 8)))
+void k_row(CavDesc d) {
     __shared__ cx<T> lds[S::LDS_ELEMS];
     __shared__ double red[4 * 16];
     row_task<S, T, MODE, MODEL>(d, blockIdx.x, lds, red);
 }
 
 template <class S, typename T, int MODE, int PROP>
-__global__ __launch_bounds__(S::THREADS) void k_col(CavDesc d) {
+__global__ __launch_bounds__(S::THREADS) __attribute__((amdgpu_waves_per_eu(one_cavity_wpe<S, T>(), 8)))
+void k_col(CavDesc d) {
     __shared__ cx<T> lds[S::LDS_ELEMS];
     if constexpr (MODE == COL_PROP) {
         // the row pass of this trip is complete (stream order): fold its

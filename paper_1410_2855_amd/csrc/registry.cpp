@@ -9,8 +9,10 @@ LSR_DECL(256) LSR_DECL(384) LSR_DECL(512) LSR_DECL(768) LSR_DECL(1024) LSR_DECL(
 const Launchers* launchers_256l();
 const Launchers* launchers_256q();
 const Launchers* launchers_256p();
+const Launchers* launchers_2048w();
 
 const Launchers* launchers_alt(int N, int k) {
+    if (N == 2048) return k == 1 ? launchers_2048w() : nullptr;
     if (N != 256) return nullptr;
     switch (k) {
     case 1:  return launchers_256l();

@@ -124,6 +124,9 @@ using L256  = Shape<256, 32, 8, 8, 8, 4>;
 // lines per workgroup: the shortest per-lane chain for a lone 256^2 cavity.
 using L256q = Shape<256, 64, 4, 4, 4, 4, 4>;
 using L256p = Shape<256, 64, 2, 4, 4, 4, 4>;
+// A wave per 2048-point line (32 points per lane): its exchanges need no
+// workgroup barrier, at two waves per SIMD.
+using L2048w = Shape<2048, 64, 4, 8, 16, 16>;
 // FP64 complex field (16 B/point): half the lines per workgroup.
 using D256  = Shape<256, 16, 8, 16, 16>;
 using D384  = Shape<384, 16, 8, 8, 12, 4>;
@@ -137,7 +140,7 @@ static_assert(S256::valid() && S384::valid() && S512::valid() && S768::valid() &
               S1024::valid() && S2048::valid() && S4096::valid(), "bad fp32 shape");
 static_assert(S512r::valid() && S1024r::valid() && S1024t::valid() && S2048r::valid() && S4096w::valid(),
               "bad alternative shape");
-static_assert(L256::valid() && L256q::valid() && L256p::valid(), "bad one-cavity shape");
+static_assert(L256::valid() && L256q::valid() && L256p::valid() && L2048w::valid(), "bad one-cavity shape");
 static_assert(D256::valid() && D384::valid() && D512::valid() && D768::valid() &&
               D1024::valid() && D2048::valid() && D4096::valid(), "bad fp64 shape");
 
