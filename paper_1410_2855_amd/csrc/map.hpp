@@ -105,6 +105,33 @@ __device__ __forceinline__ void row_chunk_pos(int c, int& l, int& x) {
     }
 }
 
+// A thread stages chunks c = tid + i THREADS.  Chunk i then lies a fixed
+// distance after chunk 0 on every lane: in a tiled row span i EPC THREADS/TT
+// whole tiles later (same line, RSTEP i positions further on), in row-major
+// rows i EPC THREADS elements later.  The advances are multiples of 16, so
+// the padded LDS slot is chunk 0's plus a compile-time offset (an immediate
+// of the LDS instruction) rather than recomputed for every chunk.
+template <class S, typename T> constexpr int RSTEP = EPC<T> * S::THREADS / S::LPW;
+// whether chunk i's slot is chunk 0's plus a constant (row-major spans: when
+// the staging stride and N divide one another)
+template <class S, typename T, int LAYOUT>
+constexpr bool row_slots_shift() {
+    constexpr int ST = EPC<T> * S::THREADS;
+    if constexpr (LAYOUT == 1) return ST % (S::LPW * S::LPW) == 0 && RSTEP<S, T> % 16 == 0;
+    else return ST % 16 == 0 && (ST % S::N == 0 || S::N % ST == 0);
+}
+template <class S, typename T, int LAYOUT>
+constexpr int row_slot_delta(int i) {
+    constexpr int ST = EPC<T> * S::THREADS;
+    if constexpr (LAYOUT == 1) {
+        return i * (RSTEP<S, T> + RSTEP<S, T> / 16);
+    } else {
+        // whole rows (i ST)/N further on, and within the row (i ST) mod N
+        // positions further on (0 when ST is a multiple of N)
+        return (i * ST / S::N) * S::LINE + (i * ST % S::N) + (i * ST % S::N) / 16;
+    }
+}
+
 // Chunks of a row span a workgroup thread stages.
 template <class S, typename T> constexpr int ROW_IT = S::LPW * S::N / EPC<T> / S::THREADS;
 
@@ -120,14 +147,29 @@ __device__ __forceinline__ void load_rows(const cx<T>* __restrict__ blk, typenam
 
 template <class S, typename T, int LAYOUT>
 __device__ __forceinline__ void commit_rows(const typename V16<T>::type* q, cx<T>* lds, int tid) {
-    sfor<0, ROW_IT<S, T>>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
+    if constexpr (row_slots_shift<S, T, LAYOUT>()) {
         int l, x;
-        row_chunk_pos<S, T, LAYOUT>(tid + i * S::THREADS, l, x);
-        cx<T> e[EPC<T>];
-        unpack16<T>(q[i], e);
-        sfor<0, EPC<T>>([&](auto kc) { lds[l * S::LINE + S::pad(x + decltype(kc)::value)] = e[decltype(kc)::value]; });
-    });
+        row_chunk_pos<S, T, LAYOUT>(tid, l, x);
+        cx<T>* base = lds + l * S::LINE + S::pad(x);   // x is a multiple of EPC: the chunk stays in a 16-block
+        sfor<0, ROW_IT<S, T>>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            cx<T> e[EPC<T>];
+            unpack16<T>(q[i], e);
+            sfor<0, EPC<T>>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                base[row_slot_delta<S, T, LAYOUT>(i) + k] = e[k];
+            });
+        });
+    } else {
+        sfor<0, ROW_IT<S, T>>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            int l, x;
+            row_chunk_pos<S, T, LAYOUT>(tid + i * S::THREADS, l, x);
+            cx<T> e[EPC<T>];
+            unpack16<T>(q[i], e);
+            sfor<0, EPC<T>>([&](auto kc) { lds[l * S::LINE + S::pad(x + decltype(kc)::value)] = e[decltype(kc)::value]; });
+        });
+    }
 }
 
 template <class S, typename T, int LAYOUT>
@@ -135,15 +177,29 @@ __device__ __forceinline__ void stage_out_rows(cx<T>* __restrict__ blk, const cx
     using V = typename V16<T>::type;
     constexpr int NCH = S::LPW * S::N / EPC<T>;
     constexpr int IT = NCH / S::THREADS;
-    sfor<0, IT>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        const int c = tid + i * S::THREADS;
+    if constexpr (row_slots_shift<S, T, LAYOUT>()) {
         int l, x;
-        row_chunk_pos<S, T, LAYOUT>(c, l, x);
-        cx<T> e[EPC<T>];
-        sfor<0, EPC<T>>([&](auto kc) { e[decltype(kc)::value] = lds[l * S::LINE + S::pad(x + decltype(kc)::value)]; });
-        gst_nt<V, 16 * i * S::THREADS>(blk, 16u * (unsigned)tid, pack16<T>(e));
-    });
+        row_chunk_pos<S, T, LAYOUT>(tid, l, x);
+        const cx<T>* base = lds + l * S::LINE + S::pad(x);
+        sfor<0, IT>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            cx<T> e[EPC<T>];
+            sfor<0, EPC<T>>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                e[k] = base[row_slot_delta<S, T, LAYOUT>(i) + k];
+            });
+            gst_nt<V, 16 * i * S::THREADS>(blk, 16u * (unsigned)tid, pack16<T>(e));
+        });
+    } else {
+        sfor<0, IT>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            int l, x;
+            row_chunk_pos<S, T, LAYOUT>(tid + i * S::THREADS, l, x);
+            cx<T> e[EPC<T>];
+            sfor<0, EPC<T>>([&](auto kc) { e[decltype(kc)::value] = lds[l * S::LINE + S::pad(x + decltype(kc)::value)]; });
+            gst_nt<V, 16 * i * S::THREADS>(blk, 16u * (unsigned)tid, pack16<T>(e));
+        });
+    }
 }
 
 // Column block cb of the tiled layout: tiles (i, cb), i = 0..N/LPW-1.
