@@ -161,6 +161,30 @@ def summarize(out_dir: str, workload: str, cavities: int, grid: int, workload_fl
     print(json.dumps(traffic, indent=1))
 
 
+def summarize_single(out_dir: str, workload: str, fft_plan: int):
+    """profiles/kernel_stats_<workload>.txt from a rocprofv3 kernel trace of
+    bench.py --workload <single...>: the one-cavity row and column kernels
+    (k_row, k_col) of its eager calls, and the batch kernels (k_pass) of the
+    graph-replayed legs, one leg per batch FFT plan of the size."""
+    import glob as _g
+
+    stats = _read_csv(_g.glob(os.path.join(out_dir, "kt", "*kernel_stats.csv"))[0])
+    cmd = ("rocprofv3 --kernel-trace --stats --output-format csv -d OUT/kt -o kt -- python3 /root/repo/bench.py "
+           "--workload %s --fft-plan %d --steps 200 --warmup 50" % (workload, fft_plan))
+    lines = ["rocprofv3 kernel statistics: %s, one-cavity FFT plan %d" % (WORKLOADS[workload], fft_plan), "",
+             "command (from /tmp, TMPDIR=/tmp): " + cmd, "",
+             "%-12s %8s %12s %12s %12s  %s" % ("share %", "calls", "avg us", "min us", "max us", "kernel")]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append("%-12.2f %8s %12.2f %12.2f %12.2f  %s" % (
+            float(r["Percentage"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, r["Name"][:160]))
+    lines += ["", "kernel source hash: " + kernel_source_hash()]
+    path = os.path.join(ROOT, "profiles", "kernel_stats_%s.txt" % workload)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(path)
+
+
 # SQ counter passes (at most 8 SQ counters per rocprofv3 run): WL as above
 SQ_PASSES = {
     "sqa": "SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE SQ_WAIT_INST_LDS SQ_WAVE_CYCLES SQ_BUSY_CYCLES "
@@ -535,8 +559,10 @@ def main():
             summarize(args.summarize, WORKLOADS["sweep1024"] % args.cavities, args.cavities, 1024)
         elif args.workload == "structured4096":
             summarize(args.summarize, WORKLOADS["structured4096"], 16, 4096, "--workload structured4096 ")
+        elif args.workload.startswith("single"):
+            summarize_single(args.summarize, args.workload, max(args.fft_plan, 0))
         else:
-            sys.exit("--summarize covers the single-size workloads (sweep1024, structured4096)")
+            sys.exit("--summarize covers the single-size and one-cavity workloads")
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: every cavity of the workload is independent and the "
