@@ -281,8 +281,17 @@ static int group_blocks(const BatchGroup& g, int N) {
     return 0;
 }
 
+// After a failed regroup or repack: no group is left half built.  The
+// recorded local-step codes are cleared too, so the next call regroups
+// (regroup_if_models_changed) or reports the failure again.
+static int groups_invalidate(lsr_batch_s* b, int rc) {
+    groups_free(b);
+    b->models.clear();
+    return rc;
+}
+
 // (Re)build the task lists of every group for the current tuning.
-static int batch_pack(lsr_batch_s* b) {
+static int batch_pack_groups(lsr_batch_s* b) {
     const int lag = b->tune.lag >= 0 ? b->tune.lag : default_lag();
     for (auto& g : b->grp) {
         std::vector<int> nrb;
@@ -296,6 +305,7 @@ static int batch_pack(lsr_batch_s* b) {
         if (g.d_last) (void)hipFree(g.d_last);
         if (g.d_cols) (void)hipFree(g.d_cols);
         g.d_tasks = g.d_last = g.d_cols = nullptr;
+        g.ntasks = g.nlast = g.ncols = 0;
         if (dev_malloc((void**)&g.d_tasks, t.size() * sizeof(int4)) != hipSuccess ||
             dev_malloc((void**)&g.d_last, l.size() * sizeof(int4)) != hipSuccess ||
             dev_malloc((void**)&g.d_cols, cols.size() * sizeof(int4)) != hipSuccess)
@@ -310,6 +320,11 @@ static int batch_pack(lsr_batch_s* b) {
     return LSR_OK;
 }
 
+static int batch_pack(lsr_batch_s* b) {
+    const int rc = batch_pack_groups(b);
+    return rc == LSR_OK ? rc : groups_invalidate(b, rc);
+}
+
 // Cavities -> groups.  merge = 0: one group per grid size (each kernel
 // specialised for its size: registers and LDS of that size only), with the
 // size's alternative FFT plan tune.shape where one is compiled; merge = 1:
@@ -317,7 +332,7 @@ static int batch_pack(lsr_batch_s* b) {
 // that covers all the part's sizes (uneven sizes advance in one launch).
 // Allocates the groups' descriptor and control blocks (and the twiddles of an
 // alternative plan) and packs their task lists.
-static int batch_partition(lsr_batch_s* b) {
+static int batch_partition_groups(lsr_batch_s* b) {
     groups_free(b);
     b->sheets = b->plans[0]->slices;
     // sizes with a cavity of another local-step code than the default run on
@@ -397,6 +412,11 @@ static int batch_partition(lsr_batch_s* b) {
             return set_err(LSR_EDEVICE, "control block upload failed");
     }
     return batch_pack(b);
+}
+
+static int batch_partition(lsr_batch_s* b) {
+    const int rc = batch_partition_groups(b);
+    return rc == LSR_OK ? rc : groups_invalidate(b, rc);
 }
 
 static int variant_of(const lsr_batch_s* b, const BatchGroup& g) {

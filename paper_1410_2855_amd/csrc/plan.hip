@@ -425,7 +425,11 @@ int lsr_plan_set_gain(lsr_plan p, double N0, double T1, double mod_amp, double m
         if (rc) return rc;
         if (p->d_pump) {
             // the old table may still be read by enqueued work
-            LSR_HIP(hipStreamSynchronize(p->stream));
+            const hipError_t e = hipStreamSynchronize(p->stream);
+            if (e != hipSuccess) {
+                (void)hipFree(t);
+                return set_err(LSR_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+            }
             (void)hipFree(p->d_pump);
         }
         p->d_pump = t;

@@ -194,3 +194,50 @@ def test_allocation_failure_returns_enomem_and_leaks_nothing(monkeypatch):
     lsr.lsr_batch_destroy(b)
     other.close()
     plan.close()
+
+
+def test_failed_regroup_leaves_no_half_built_batch():
+    """A batch whose regrouping (sizes merged into one kernel) or repacking
+    (another lag) fails on a device allocation, forced from the host at
+    every allocation in turn, reports LSR_ENOMEM; its next call regroups and
+    every cavity then advances bitwise as on the one-cavity path."""
+    from paper_1410_2855_amd.inputs import Cavity
+
+    cavs = [Cavity(N=1024, F=300.0, R=0.9, pump_ratio=2.0, T1=500.0, index=20),
+            Cavity(N=512, F=200.0, R=0.92, pump_ratio=2.5, T1=700.0, index=21)]
+    ref = []
+    for c in cavs:
+        p = lsr.Plan(c)
+        e, n = p.state(*initial_state(c))
+        p.roundtrips(e, n, 6)
+        p.sync()
+        ref.append((e, n))
+        p.close()
+    for change in (dict(merge=1), dict(lag=3)):
+        for k in range(32):
+            plans = [lsr.Plan(c) for c in cavs]
+            st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+            Es, Ns = [x[0] for x in st], [x[1] for x in st]
+            b = lsr.lsr_batch_create([p.handle for p in plans])
+            lsr.lsr_batch_roundtrips(b, Es, Ns, 3)
+            lsr.lsr_test_fail_alloc(k)
+            try:
+                lsr.lsr_batch_configure(b, **change)
+                failed = False
+            except lsr.LsrError as err:
+                assert err.code == lsr.LSR_ENOMEM, (change, k, err)
+                failed = True
+            finally:
+                lsr.lsr_test_fail_alloc(-1)
+            lsr.lsr_batch_roundtrips(b, Es, Ns, 3)
+            for p in plans:
+                p.sync()
+            for j in range(len(cavs)):
+                assert torch.equal(Es[j], ref[j][0]) and torch.equal(Ns[j], ref[j][1]), (change, k, j)
+            lsr.lsr_batch_destroy(b)
+            for p in plans:
+                p.close()
+            if not failed:
+                break
+        else:
+            raise AssertionError("configure never succeeded: %s" % change)
