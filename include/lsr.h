@@ -187,9 +187,12 @@ int lsr_plan_set_fft_plan(lsr_plan p, int k);
  * (or the filter of lsr_plan_set_filter).  The plan keeps T/N^2 by column in
  * its precision (8 B per point, 16 for FP64 plans), read by the column pass
  * in every precision form: the column pass then moves 8 (16) more bytes per
- * point.  One gain sheet only (LSR_EINVAL with several); batches refuse such
- * plans (LSR_EUNSUPPORTED).  Waits for the plan's stream and allocates the
- * table (the previous one is freed).  LSR_EINVAL for a non-finite value. */
+ * point.  One gain sheet only (LSR_EINVAL with several).  Batches run such
+ * plans on the kernels that read each cavity's local-step code, whose column
+ * tasks then take the cavity's table; setting or clearing T regroups a batch
+ * holding the plan on its next call.  Waits for the plan's stream and
+ * allocates the table (the previous one is freed).  LSR_EINVAL for a
+ * non-finite value. */
 int lsr_plan_set_transfer(lsr_plan p, const double* T);
 
 /* Several thin gain sheets per round trip: the active medium spread along
@@ -328,9 +331,8 @@ void lsr_plan_destroy(lsr_plan p);
  * stream (LSR_EINVAL otherwise, here and in every later call that finds a
  * plan rebound to another one).  Errors: LSR_EINVAL for a NULL out or plan,
  * count < 1, a plan given twice or plans on different devices;
- * LSR_EUNSUPPORTED for plans other than the FP64TAB form, plans with
- * different numbers of gain sheets, or a plan with a general transfer
- * function (lsr_plan_set_transfer); LSR_ENOMEM / LSR_EDEVICE when its
+ * LSR_EUNSUPPORTED for plans other than the FP64TAB form or plans with
+ * different numbers of gain sheets; LSR_ENOMEM / LSR_EDEVICE when its
  * tables or task lists cannot be allocated or uploaded (nothing is leaked;
  * *out is then NULL). */
 int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count);

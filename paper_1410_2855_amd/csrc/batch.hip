@@ -225,7 +225,8 @@ struct lsr_batch_s {
     std::vector<BatchGroup> grp;
     std::vector<void*> lastE, lastN;
     std::vector<unsigned> lastVer;   // plan descriptor versions of the last upload
-    std::vector<int> models;         // the plans' local-step codes (model, roughness) when grouped
+    std::vector<int> models;         // the plans' group codes (model, roughness, transfer
+                                     // function) when grouped
     int sheets = 1;                  // gain sheets per round trip, the same for every plan
     Tune tune;
     std::string key;
@@ -281,6 +282,10 @@ static int group_blocks(const BatchGroup& g, int N) {
     return 0;
 }
 
+// What a plan's group must compile in: its local-step code (model,
+// roughness) and whether it has a general transfer function.
+static int group_code(const lsr_plan_s* q) { return q->d.model | (q->d_trans ? 1 << 8 : 0); }
+
 // After a failed regroup or repack: no group is left half built.  The
 // recorded local-step codes are cleared too, so the next call regroups
 // (regroup_if_models_changed) or reports the failure again.
@@ -335,22 +340,29 @@ static int batch_pack(lsr_batch_s* b) {
 static int batch_partition_groups(lsr_batch_s* b) {
     groups_free(b);
     b->sheets = b->plans[0]->slices;
-    // sizes with a cavity of another local-step code than the default run on
-    // kernels for that size alone (key -(64N + level)): level ANY_FIXED + m
-    // when every cavity of the size has model m and a smooth mirror, else 1
-    // (kernels that read each cavity's model) or 2 when one has a rough
-    // mirror (model and roughness read per cavity)
+    // sizes with a cavity of another local-step code than the default, or
+    // with a general transfer function, run on kernels for that size alone
+    // (key -(64N + level)): level ANY_FIXED + m when every cavity of the size
+    // has model m, a smooth mirror and the propagator or filter, else 1
+    // (kernels that read each cavity's model and propagator kind) or 2 when
+    // one has a rough mirror (model and roughness read per cavity)
     b->models.clear();
     std::map<int, int> level;
     std::map<int, std::set<int>> codes;
+    std::set<int> with_trans;
     for (auto* q : b->plans) {
-        b->models.push_back(q->d.model);
-        const int l = (q->d.model & MODEL_ROUGH) ? 2 : q->d.model != 0 ? 1 : 0;
+        b->models.push_back(group_code(q));
+        int l = (q->d.model & MODEL_ROUGH) ? 2 : q->d.model != 0 ? 1 : 0;
+        if (q->d_trans) {
+            l = std::max(l, 1);
+            with_trans.insert(q->N);
+        }
         level[q->N] = std::max(level[q->N], l);
         codes[q->N].insert(q->d.model);
     }
     for (auto& kv : level)
-        if (kv.second == 1 && codes[kv.first].size() == 1) kv.second = ANY_FIXED + *codes[kv.first].begin();
+        if (kv.second == 1 && codes[kv.first].size() == 1 && !with_trans.count(kv.first))
+            kv.second = ANY_FIXED + *codes[kv.first].begin();
     std::map<int, std::vector<int>> parts;
     for (int i = 0; i < (int)b->plans.size(); ++i) {
         ShapeInfo s;
@@ -587,6 +599,10 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
             const bool runs = lvl >= ANY_FIXED ? d.model == lvl - ANY_FIXED
                             : lvl == 2 ? true : lvl == 1 ? (d.model & MODEL_ROUGH) == 0 : d.model == 0;
             if (!runs) return set_err(LSR_EINVAL, "cavity %d: local-step code %d not in its group", c, d.model);
+            if (d.prop_kind == 2 && (lvl != 1 && lvl != 2))
+                return set_err(LSR_EINVAL, "cavity %d: general transfer function not in its group", c);
+            if ((d.prop_kind == 2) != (d.trans != nullptr))
+                return set_err(LSR_EINVAL, "cavity %d: propagator kind and transfer table disagree", c);
             for (int z = 0; z < g.g->nsizes; ++z)
                 if (g.g->sizes[z] == d.N) d.tw = g.d_tw[z];
             d.nrb = group_blocks(g, d.N);
@@ -602,11 +618,12 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
     return LSR_OK;
 }
 
-// A plan's local-step code (model, roughness) changed since the batch was
-// grouped: regroup (the kernels of a group read the codes it was built for).
+// A plan's local-step code (model, roughness) or its general transfer
+// function changed since the batch was grouped: regroup (the kernels of a
+// group read the codes it was built for).
 static int regroup_if_models_changed(lsr_batch_s* b) {
     bool same = b->models.size() == b->plans.size() && b->sheets == b->plans[0]->slices;
-    for (size_t i = 0; same && i < b->plans.size(); ++i) same = b->models[i] == b->plans[i]->d.model;
+    for (size_t i = 0; same && i < b->plans.size(); ++i) same = b->models[i] == group_code(b->plans[i]);
     if (same) return LSR_OK;
     LSR_HIP(hipStreamSynchronize(b->stream));
     drop_graphs(b);
@@ -689,8 +706,6 @@ int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count) {
         if (plans[i]->device != plans[0]->device) return set_err(LSR_EINVAL, "plans on different devices");
         if (plans[i]->slices != plans[0]->slices)
             return set_err(LSR_EUNSUPPORTED, "plan %d: every plan of a batch must have the same number of gain sheets", i);
-        if (plans[i]->d_trans)
-            return set_err(LSR_EUNSUPPORTED, "plan %d: batches run the propagator or the filter, not a general transfer function", i);
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return set_err(LSR_EINVAL, "plan %d appears twice", i);
         if (plans[i]->stream != plans[0]->stream)
@@ -798,8 +813,6 @@ int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* N, int n_trip
             return set_err(LSR_EINVAL, "state %zu: NULL or not 16-byte aligned", i);
         if (b->plans[i]->slices != b->plans[0]->slices)
             return set_err(LSR_EUNSUPPORTED, "plan %zu: every plan of a batch must have the same number of gain sheets", i);
-        if (b->plans[i]->d_trans)
-            return set_err(LSR_EUNSUPPORTED, "plan %zu: batches run the propagator or the filter, not a general transfer function", i);
     }
     if (check_streams(b)) return LSR_EINVAL;
     if (n_trips == 0) return LSR_OK;

@@ -51,6 +51,12 @@ struct Group {
 // batch puts no rough cavity in the others).  ANY = ANY_FIXED + m: model m
 // alone, compiled in (groups whose cavities all have model m and a smooth
 // mirror; no switch, so no registers of the other bodies).
+// Kernels that read each cavity's code (ANY = 1, 2) also take a cavity's
+// general transfer function (prop_kind 2, the map with kernel K of Eq. (10))
+// in their column tasks: a uniform branch per task.
+template <int ANY>
+constexpr bool takes_trans() { return ANY == 1 || ANY == 2; }
+
 template <int MODE, int ANY, class S>
 __device__ __forceinline__ bool run_if(const CavDesc& d, int kind, int blk, unsigned char* smem, double* red) {
     if (d.N != S::N) return false;
@@ -76,6 +82,8 @@ __device__ __forceinline__ bool run_if(const CavDesc& d, int kind, int blk, unsi
         } else {
             row_task<S, float, MODE>(d, blk, lds, red);
         }
+    } else if (takes_trans<ANY>() && d.prop_kind == 2) {
+        col_task<S, float, COL_PROP, PROP_TRANS>(d, blk, lds);
     } else {
         col_task<S, float, COL_PROP>(d, blk, lds);
     }
@@ -181,9 +189,15 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
 // Column tasks of single-size groups bring the cavity's propagator table hx
 // into LDS together with their tile, so the propagator multiply in the middle
 // of the transforms reads LDS instead of waiting on global loads.
-template <class S>
+template <int ANY, class S>
 __device__ __forceinline__ void col_task_hx_lds(const CavDesc& d, int cb, unsigned char* smem) {
     cx<float>* lds = reinterpret_cast<cx<float>*>(smem);
+    if constexpr (takes_trans<ANY>()) {
+        if (d.prop_kind == 2) {
+            col_task<S, float, COL_PROP, PROP_TRANS>(d, cb, lds);
+            return;
+        }
+    }
     ColRegs<S, float, true> in;
     col_load<S, float, COL_PROP, true>(d, cb, in);
     col_body<S, float, COL_PROP, PROP_TABLE, TW_GLOBAL, true>(d, cb, lds, in, [] {}, nullptr,
@@ -212,7 +226,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(WPE, 8)
         // gain sheets carry no trace)
         if (blk == 0 && threadIdx.x < 64 && d.trace) finalize_sums(d);
     }
-    if constexpr (HXLDS) (col_task_hx_lds<Ss>(d, blk, smem), ...);
+    if constexpr (HXLDS) (col_task_hx_lds<ANY, Ss>(d, blk, smem), ...);
     else (run_if<MODE, ANY, Ss>(d, KIND, blk, smem, red) || ...);
 }
 

@@ -1,7 +1,7 @@
 """A general nonlocal step, the map with kernel K of Eq. (10), given by its
 transfer function (lsr_plan_set_transfer), on the GPU against the FP64
-oracle, against the exact shift of a point kernel, and the boundary's
-refusals."""
+oracle, against the exact shift of a point kernel, in batches against the
+one-cavity path, and the boundary's refusals."""
 import numpy as np
 import pytest
 
@@ -91,11 +91,8 @@ def test_transfer_cleared_restores_the_propagator_and_refusals():
     ref.sync()
     p = lsr.Plan(cav)
     lsr.lsr_plan_set_transfer(p.handle, kernel_transfer(skewed_kernel(256, cav.dx), cav.dx))
-    # batches run the propagator or the filter only; several sheets are refused
+    # several gain sheets are refused
     other = lsr.Plan(cav.with_(index=78))
-    with pytest.raises(lsr.LsrError) as ei:
-        lsr.lsr_batch_create([p.handle, other.handle])
-    assert ei.value.code == lsr.LSR_EUNSUPPORTED
     with pytest.raises(lsr.LsrError) as ei:
         lsr.lsr_plan_set_slices(p.handle, 2)
     assert ei.value.code == lsr.LSR_EINVAL
@@ -111,3 +108,80 @@ def test_transfer_cleared_restores_the_propagator_and_refusals():
     assert torch.equal(e, er) and torch.equal(n, nr)
     for q in (p, other, ref):
         q.close()
+
+
+@pytest.mark.parametrize("engine,graph_k", [(0, 0), (1, 0), (1, 4), (2, 4)])
+def test_batch_with_general_kernels_is_bitwise_the_one_cavity_path(engine, graph_k):
+    """Batches holding plans with a general transfer function, beside plans
+    of the same size (default and exact-update local steps) and of another
+    size, on every engine, with and without graphs: every cavity advances
+    bitwise as on the one-cavity path.  Setting the function on another plan
+    and clearing it on the first between calls regroups the batch, and the
+    cavities still follow the one-cavity path with the same changes."""
+    base = cavity(256)
+    cavs = [base.with_(index=80), base.with_(index=81), base.with_(index=82, model=1),
+            cavity(512).with_(index=83)]
+    T = {256: kernel_transfer(skewed_kernel(256, base.dx), base.dx)}
+    T[512] = kernel_transfer(skewed_kernel(512, cavs[3].dx, total=0.95), cavs[3].dx)
+    first = {0: True, 1: False, 2: False, 3: True}    # which plans carry T in the first calls
+    second = {0: False, 1: True, 2: False, 3: True}   # and after the change
+    calls1, calls2 = (3, 4), (3,)
+
+    def apply(p, c, on):
+        lsr.lsr_plan_set_transfer(p.handle, T[c.N] if on else None)
+
+    ref = []
+    for j, c in enumerate(cavs):
+        p = lsr.Plan(c)
+        apply(p, c, first[j])
+        e, n = p.state(*initial_state(c))
+        p.roundtrips(e, n, sum(calls1))
+        apply(p, c, second[j])
+        p.roundtrips(e, n, sum(calls2))
+        p.sync()
+        ref.append((e, n))
+        p.close()
+    plans = [lsr.Plan(c) for c in cavs]
+    for j, (p, c) in enumerate(zip(plans, cavs)):
+        apply(p, c, first[j])
+    st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+    Es, Ns = [x[0] for x in st], [x[1] for x in st]
+    b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_configure(b, engine=engine, graph_k=graph_k)
+    for k in calls1:
+        lsr.lsr_batch_roundtrips(b, Es, Ns, k)
+    for j, (p, c) in enumerate(zip(plans, cavs)):
+        if second[j] != first[j]:
+            apply(p, c, second[j])
+    for k in calls2:
+        lsr.lsr_batch_roundtrips(b, Es, Ns, k)
+    for p in plans:
+        p.sync()
+    for j in range(len(cavs)):
+        assert torch.equal(Es[j], ref[j][0]) and torch.equal(Ns[j], ref[j][1]), (engine, graph_k, j)
+    lsr.lsr_batch_destroy(b)
+    for p in plans:
+        p.close()
+
+
+def test_batched_general_kernel_matches_the_oracle():
+    """50 batched trips of a cavity with a general transfer function beside
+    a default cavity of its size, against the FP64 oracle."""
+    cav = cavity(256)
+    T = kernel_transfer(skewed_kernel(256, cav.dx), cav.dx)
+    p = lsr.Plan(cav)
+    lsr.lsr_plan_set_transfer(p.handle, T)
+    q = lsr.Plan(cav.with_(index=90))
+    (e, n), (e2, n2) = p.state(*initial_state(cav)), q.state(*initial_state(cav.with_(index=90)))
+    b = lsr.lsr_batch_create([p.handle, q.handle])
+    lsr.lsr_batch_roundtrips(b, [e, e2], [n, n2], 50)
+    p.sync()
+    tr = p.trace(50)
+    lsr.lsr_batch_destroy(b)
+    par = oracle_params(cav)
+    par.transfer = T
+    eo, no, to = oracle.run(par, *initial_state(cav), 50)
+    assert rel(e.cpu().numpy(), eo) <= 1e-5 and rel(n.cpu().numpy(), no) <= 1e-5
+    assert rel(tr, to) <= 1e-5
+    p.close()
+    q.close()
