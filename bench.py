@@ -161,6 +161,92 @@ def summarize(out_dir: str, workload: str, cavities: int, grid: int, workload_fl
     print(json.dumps(traffic, indent=1))
 
 
+# Cavity counts of the working-set sweep (--cache-sweep): 12.6 MB of state
+# (FP32 field and inversion) per 1024^2 cavity, from 12.6 MB to 805 MB.
+CACHE_SWEEP_COUNTS = (1, 2, 4, 8, 12, 16, 20, 24, 32, 48, 64)
+CACHE_SWEEP_CMD = ("rocprofv3 --kernel-trace --output-format csv -d OUT/kt -o kt -- python3 /root/repo/bench.py "
+                   "--cache-sweep")
+
+
+def bench_cache_sweep(args):
+    """The batched 1024^2 map on the first c cavities of the sweep workload,
+    c in CACHE_SWEEP_COUNTS (grouped engine, default FFT plan), each pass
+    timed by dispatch events over 200 eager trips after about 0.3 s of
+    untimed ones.  While the state a pass
+    streams fits the Infinity Cache, a pass reads what the previous pass
+    left there; beyond it the passes run at the HBM rate.  One JSON line per
+    count: pass durations and the algorithmic bytes per second."""
+    import torch
+
+    from paper_1410_2855_amd import lsr
+    from paper_1410_2855_amd.inputs import initial_state, sweep_1024
+
+    lsr.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    every = sweep_1024(max(CACHE_SWEEP_COUNTS))
+    for c in CACHE_SWEEP_COUNTS:
+        cavs = every[:c]
+        plans = [lsr.Plan(cv, prec=lsr.LSR_PREC_FP64TAB, stream=stream) for cv in cavs]
+        st = [p.state(*initial_state(cv), device=dev) for p, cv in zip(plans, cavs)]
+        Es, Ns = [x[0] for x in st], [x[1] for x in st]
+        b = lsr.lsr_batch_create([p.handle for p in plans])
+        lsr.lsr_batch_configure(b, engine=1, graph_k=0, shape=0)
+        # about 0.3 s of trips first, so that the clocks have settled under load
+        lsr.lsr_batch_roundtrips(b, Es, Ns, max(50, 36000 // c))
+        row_ms, col_ms, trip_ms = lsr.lsr_batch_time_kernels(b, Es, Ns, 200)
+        torch.cuda.synchronize()
+        lsr.lsr_batch_destroy(b)
+        for p in plans:
+            p.close()
+        pts = c * 1024 * 1024
+        print(json.dumps({"cavities": c, "state_MB": round(pts * 12 / 1e6, 1),
+                          "row_us": round(row_ms * 1e3, 2), "column_us": round(col_ms * 1e3, 2),
+                          "row_GBps": round(ROW_BYTES_PER_PT * pts / row_ms / 1e6, 1),
+                          "column_GBps": round(COL_BYTES_PER_PT * pts / col_ms / 1e6, 1),
+                          "trip_GBps": round(TRIP_BYTES_PER_PT * pts / trip_ms / 1e6, 1)}), flush=True)
+        del Es, Ns, st
+        torch.cuda.empty_cache()
+
+
+def summarize_cache(out_dir: str):
+    """profiles/cache_sweep_1024.txt from a rocprofv3 kernel trace of
+    bench.py --cache-sweep: per cavity count (the launch's task count over
+    1024/4 row or column blocks per cavity), the average duration of the
+    middle-trip row and column passes and their algorithmic bytes per second."""
+    import glob as _g
+
+    rows = _read_csv(_g.glob(os.path.join(out_dir, "kt", "*kernel_trace.csv"))[0])
+    acc = {}
+    for r in rows:
+        for k, pat in PASS_KERNELS.items():
+            if pat in r["Kernel_Name"] and "Shape<1024," in r["Kernel_Name"]:
+                tasks = int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"])
+                d = acc.setdefault((tasks // 256, k), [])
+                d.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = ["Working-set sweep of the batched map: the first c cavities of the 1024^2 sweep workload, "
+             "FP64-table form, grouped engine; middle-trip passes of the warm-up and the 200 timed eager trips "
+             "per count", "",
+             "command (from /tmp, TMPDIR=/tmp): " + CACHE_SWEEP_CMD, "",
+             "%9s %9s %9s %10s %12s %10s %12s" % ("cavities", "state MB", "launches", "row us", "row GB/s",
+                                                 "column us", "column GB/s")]
+    for c in sorted({c for c, _ in acc}):
+        rw, cl = acc.get((c, "row_pass"), []), acc.get((c, "column_pass"), [])
+        if not rw or not cl:
+            continue
+        pts = c * 1024 * 1024
+        ra, ca = sum(rw) / len(rw), sum(cl) / len(cl)
+        lines.append("%9d %9.1f %9d %10.2f %12.1f %10.2f %12.1f" % (
+            c, pts * 12 / 1e6, len(rw), ra, ROW_BYTES_PER_PT * pts / ra / 1e3, ca, COL_BYTES_PER_PT * pts / ca / 1e3))
+    lines += ["", "state MB: FP32 field and inversion, 12 B per point; GB/s: algorithmic bytes (24 B/pt row, "
+              "16 B/pt column) over the kernel-trace average", "kernel source hash: " + kernel_source_hash()]
+    path = os.path.join(ROOT, "profiles", "cache_sweep_1024.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(path)
+
+
 def summarize_single(out_dir: str, workload: str, fft_plan: int):
     """profiles/kernel_stats_<workload>.txt from a rocprofv3 kernel trace of
     bench.py --workload <single...>: the one-cavity row and column kernels
@@ -531,12 +617,21 @@ def main():
                     help="write profiles/traffic_requests_*.txt from the request-counter runs under OUT (no GPU)")
     ap.add_argument("--summarize-sq", metavar="OUT",
                     help="write profiles/sq_counters_*.txt from the SQ counter runs under OUT (no GPU)")
+    ap.add_argument("--cache-sweep", action="store_true",
+                    help="time the batched 1024^2 passes for growing cavity counts (12.6 MB to 805 MB of "
+                         "state), one JSON line per count")
+    ap.add_argument("--summarize-cache", metavar="OUT",
+                    help="write profiles/cache_sweep_1024.txt from a kernel trace of --cache-sweep under OUT "
+                         "(no GPU)")
     ap.add_argument("--oracle-sizes", action="store_true",
                     help="time the single-threaded FP64 oracle per round trip at every grid size "
                          "(host only, no GPU) and print one JSON line")
     args = ap.parse_args()
     if args.oracle_sizes:
         print(json.dumps(oracle_per_size()), flush=True)
+        return
+    if args.summarize_cache:
+        summarize_cache(args.summarize_cache)
         return
     if args.summarize_ea:
         if args.workload == "sweep1024":
@@ -572,6 +667,9 @@ def main():
     os.environ.setdefault("LSR_TUNE_CACHE", TUNE_CACHE)
     if args.workload.startswith("single"):
         bench_single(args)
+        return
+    if args.cache_sweep:
+        bench_cache_sweep(args)
         return
 
     import numpy as np

@@ -84,3 +84,32 @@ def test_summary_scales_each_counter_by_the_copy(tmp_path, monkeypatch):
     json.dump(t, open(tmp_path / "profiles" / "traffic.json", "w"))
     assert bench.load_traffic("row_pass", pts) is None
     assert bench.load_traffic("no_such_kernel", pts) is None
+
+
+def test_cache_sweep_summary_groups_the_passes_by_cavity_count(tmp_path, monkeypatch):
+    """The working-set summary takes each middle-trip pass's cavity count
+    from its launch size (one task per four-line block, 256 per 1024^2
+    cavity) and its bandwidth from the algorithmic bytes."""
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "profiles")
+    out = str(tmp_path / "out")
+    hdr = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Workgroup_Size_X", "Grid_Size_X"]
+    rows = []
+    t = 0
+    for c, row_ns, col_ns in ((2, 10000, 8000), (8, 30000, 20000)):
+        for _ in range(3):
+            rows.append([ROW, t, t + row_ns, 256, c * 256 * 256])
+            rows.append([COL, t, t + col_ns, 256, c * 256 * 256])
+            t += 100000
+    rows.append([ROW.replace("k_pass<1, 0,", "k_pass<0, 0,"), 0, 5, 256, 2 * 256 * 256])   # a first-trip pass
+    _write_csv(os.path.join(out, "kt", "kt_kernel_trace.csv"), hdr, rows)
+    bench.summarize_cache(out)
+    txt = open(tmp_path / "profiles" / "cache_sweep_1024.txt").read().split("\n")
+    table = [l.split() for l in txt if l.strip() and l.split()[0].isdigit()]
+    assert [int(r[0]) for r in table] == [2, 8]
+    two, eight = table
+    assert int(two[2]) == 3 and float(two[3]) == 10.0 and float(two[5]) == 8.0
+    pts = 8 * 1024 * 1024
+    assert float(eight[4]) == pytest.approx(24 * pts / 30e-6 / 1e9, rel=1e-3)
+    assert float(eight[6]) == pytest.approx(16 * pts / 20e-6 / 1e9, rel=1e-3)
+    assert "kernel source hash: " + bench.kernel_source_hash() in txt
