@@ -81,9 +81,10 @@ BATCH_CASES = 6
 @pytest.mark.parametrize("i", range(BATCH_CASES))
 def test_random_batch_is_bitwise_the_one_cavity_path(i):
     """Batches of randomly drawn cavities (the draws above with sizes up to
-    2048, one sheet count per batch, the FP64-table form batches take), on a
-    random engine and graph length, in calls of random lengths: every
-    cavity bitwise the one-cavity path over the same trips."""
+    2048, one sheet count per batch, the FP64-table form batches take; with
+    one sheet, some cavities with a general transfer function), on a random
+    engine and graph length, in calls of random lengths: every cavity
+    bitwise the one-cavity path over the same trips."""
     r = np.random.default_rng(7000 + i)
     m = int(r.choice([1, 1, 2, 3]))
     cavs = []
@@ -94,15 +95,27 @@ def test_random_batch_is_bitwise_the_one_cavity_path(i):
     graph_k = int(r.choice([0, 2, 5, 16]))
     calls = [int(x) for x in r.integers(1, 9, size=3)]
     trips = sum(calls)
-    ref = []
-    for c in cavs:
+    # general transfer functions (a random-phase all-pass of gain 0.98), from
+    # a generator of their own so that the draws above stay as they were
+    rt = np.random.default_rng(7500 + i)
+    trans = [rt.random() < 0.4 and m == 1 for _ in cavs]
+    tables = [0.98 * np.exp(2j * np.pi * rt.random((c.N, c.N))) if t else None for c, t in zip(cavs, trans)]
+
+    def plan_of(c, t):
         p = lsr.Plan(c)
+        if t is not None:
+            lsr.lsr_plan_set_transfer(p.handle, t)
+        return p
+
+    ref = []
+    for c, t in zip(cavs, tables):
+        p = plan_of(c, t)
         e, n = p.state(*initial_state(c))
         p.roundtrips(e, n, trips)
         p.sync()
         ref.append((e, n))
         p.close()
-    plans = [lsr.Plan(c) for c in cavs]
+    plans = [plan_of(c, t) for c, t in zip(cavs, tables)]
     st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
     Es, Ns = [x[0] for x in st], [x[1] for x in st]
     b = lsr.lsr_batch_create([p.handle for p in plans])
@@ -111,8 +124,8 @@ def test_random_batch_is_bitwise_the_one_cavity_path(i):
         lsr.lsr_batch_roundtrips(b, Es, Ns, k)
     for p in plans:
         p.sync()
-    case = "sheets=%d engine=%d graph_k=%d calls=%s sizes=%s models=%s" % (
-        m, engine, graph_k, calls, [c.N for c in cavs], [c.model for c in cavs])
+    case = "sheets=%d engine=%d graph_k=%d calls=%s sizes=%s models=%s transfer=%s" % (
+        m, engine, graph_k, calls, [c.N for c in cavs], [c.model for c in cavs], trans)
     for j in range(len(cavs)):
         assert torch.equal(Es[j], ref[j][0]) and torch.equal(Ns[j], ref[j][1]), "%s cavity %d" % (case, j)
     lsr.lsr_batch_destroy(b)
