@@ -210,11 +210,12 @@ int lsr_plan_set_transfer(lsr_plan p, const double* T);
  * values, sheet k at element offset k*N*N; lsr_diag reads sheet 0; the trace
  * holds sheet 0's sums.  Launches: 2m per trip plus 1.  Waits for the plan's
  * stream and allocates the table of the step (the previous one is freed).
- * Batches run plans of several sheets when every plan of the batch has the
- * same m (each sheet step is one grouped row pass and one grouped column
- * pass over all cavities, or one persistent launch); lsr_batch_create and
- * lsr_batch_roundtrips return LSR_EUNSUPPORTED when the counts differ, and
- * lsr_batch_time_kernels for m > 1.
+ * Batches run plans of any sheet counts together: the plans of one count
+ * form groups whose sheet step k is one grouped row pass and one grouped
+ * column pass over their cavities (or one persistent launch), and step k
+ * launches the groups with more than k sheets; a changed count regroups the
+ * batch on its next call.  lsr_batch_time_kernels returns LSR_EUNSUPPORTED
+ * for a batch holding a plan with m > 1.
  * LSR_EINVAL unless 1 <= m <= LSR_MAX_SLICES. */
 #define LSR_MAX_SLICES 64
 int lsr_plan_set_slices(lsr_plan p, int m);
@@ -331,10 +332,9 @@ void lsr_plan_destroy(lsr_plan p);
  * stream (LSR_EINVAL otherwise, here and in every later call that finds a
  * plan rebound to another one).  Errors: LSR_EINVAL for a NULL out or plan,
  * count < 1, a plan given twice or plans on different devices;
- * LSR_EUNSUPPORTED for plans other than the FP64TAB form or plans with
- * different numbers of gain sheets; LSR_ENOMEM / LSR_EDEVICE when its
- * tables or task lists cannot be allocated or uploaded (nothing is leaked;
- * *out is then NULL). */
+ * LSR_EUNSUPPORTED for plans other than the FP64TAB form; LSR_ENOMEM /
+ * LSR_EDEVICE when its tables or task lists cannot be allocated or uploaded
+ * (nothing is leaked; *out is then NULL). */
 int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count);
 
 /* Advance cavity i's state (E[i], Ninv[i]: device buffers laid out as for
@@ -345,9 +345,10 @@ int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count);
  * each plan's trace ring.  E and Ninv hold one pointer per plan, in the
  * order of lsr_batch_create.  Errors: LSR_EINVAL for a NULL batch, array or
  * state pointer, a pointer not 16-byte aligned, n_trips < 0 or a plan bound
- * to another stream; LSR_EUNSUPPORTED when a plan's number of gain sheets or
- * nonlocal step changed to one the batch cannot run; LSR_EDEVICE when a
- * launch fails.  A non-finite state is reported by lsr_sync of its plan. */
+ * to another stream; LSR_ENOMEM when a plan's changed local step, nonlocal
+ * step or number of gain sheets needs a regrouping that cannot allocate;
+ * LSR_EDEVICE when a launch fails.  A non-finite state is reported by
+ * lsr_sync of its plan. */
 int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* Ninv, int n_trips);
 
 /* Diagnostics of cavity idx of the batch; same as lsr_diag on its plan. */

@@ -209,6 +209,7 @@ struct BatchGroup {
     int nlast = 0;
     int4* d_cols = nullptr;          // column tasks only (grouped column pass)
     int ncols = 0;
+    int sheets = 1;                  // gain sheets per round trip of the group's cavities
     unsigned* d_ctrl = nullptr;
     void* d_tw[8] = {};              // twiddles of each size of the group, for its FFT plan
     int occ[4] = {1, 1, 1, 1};   // resident workgroups per CU of each variant
@@ -227,7 +228,6 @@ struct lsr_batch_s {
     std::vector<unsigned> lastVer;   // plan descriptor versions of the last upload
     std::vector<int> models;         // the plans' group codes (model, roughness, transfer
                                      // function) when grouped
-    int sheets = 1;                  // gain sheets per round trip, the same for every plan
     Tune tune;
     std::string key;
     // captured launch sequences, reused across calls (see run_trips)
@@ -282,9 +282,9 @@ static int group_blocks(const BatchGroup& g, int N) {
     return 0;
 }
 
-// What a plan's group must compile in: its local-step code (model,
-// roughness) and whether it has a general transfer function.
-static int group_code(const lsr_plan_s* q) { return q->d.model | (q->d_trans ? 1 << 8 : 0); }
+// What a plan's group must match: its local-step code (model, roughness),
+// whether it has a general transfer function, and its number of gain sheets.
+static int group_code(const lsr_plan_s* q) { return q->d.model | (q->d_trans ? 1 << 8 : 0) | (q->slices << 9); }
 
 // After a failed regroup or repack: no group is left half built.  The
 // recorded local-step codes are cleared too, so the next call regroups
@@ -339,7 +339,6 @@ static int batch_pack(lsr_batch_s* b) {
 // alternative plan) and packs their task lists.
 static int batch_partition_groups(lsr_batch_s* b) {
     groups_free(b);
-    b->sheets = b->plans[0]->slices;
     // sizes with a cavity of another local-step code than the default, or
     // with a general transfer function, run on kernels for that size alone
     // (key -(64N + level)): level ANY_FIXED + m when every cavity of the size
@@ -363,19 +362,22 @@ static int batch_partition_groups(lsr_batch_s* b) {
     for (auto& kv : level)
         if (kv.second == 1 && codes[kv.first].size() == 1 && !with_trans.count(kv.first))
             kv.second = ANY_FIXED + *codes[kv.first].begin();
-    std::map<int, std::vector<int>> parts;
+    // one group per number of gain sheets too: a group's sheet steps are its
+    // launches, sheet-major descriptors of its cavities
+    std::map<std::pair<int, int>, std::vector<int>> parts;
     for (int i = 0; i < (int)b->plans.size(); ++i) {
         ShapeInfo s;
         shape_for(b->plans[i]->N, false, &s);
         const int N = b->plans[i]->N;
-        parts[level[N] ? -(64 * N + level[N]) : b->tune.merge ? s.threads : N].push_back(i);
+        parts[{b->plans[i]->slices, level[N] ? -(64 * N + level[N]) : b->tune.merge ? s.threads : N}].push_back(i);
     }
     for (auto& kv : parts) {
         const GroupInfo* best = nullptr;
-        const bool any = kv.first < 0;
-        const int any_level = any ? (-kv.first) % 64 : 0;
+        const int sheets = kv.first.first, pkey = kv.first.second;
+        const bool any = pkey < 0;
+        const int any_level = any ? (-pkey) % 64 : 0;
         const bool merged = b->tune.merge && !any;
-        const int key = any ? (-kv.first) / 64 : kv.first;
+        const int key = any ? (-pkey) / 64 : pkey;
         const int want = (merged || any) ? 0 : b->tune.shape;
         for (int pass = 0; pass < 2 && !best; ++pass)
         for (int gi = 0; gi < group_count() && !best; ++gi) {
@@ -396,6 +398,7 @@ static int batch_partition_groups(lsr_batch_s* b) {
         BatchGroup bg;
         bg.g = best;
         bg.cav = kv.second;
+        bg.sheets = sheets;
         for (int v = 0; v < best->nvariants; ++v) {
             bg.occ[v] = best->var[v].occupancy();
             if (best->var[v].occupancy_pipe) {
@@ -406,7 +409,7 @@ static int batch_partition_groups(lsr_batch_s* b) {
         const size_t ncav = bg.cav.size();
         b->grp.push_back(bg);
         BatchGroup& g = b->grp.back();
-        if (dev_malloc((void**)&g.d_desc, (size_t)b->sheets * ncav * sizeof(CavDesc)) != hipSuccess ||
+        if (dev_malloc((void**)&g.d_desc, (size_t)g.sheets * ncav * sizeof(CavDesc)) != hipSuccess ||
             dev_malloc((void**)&g.d_ctrl, (CTRL_ROWDONE + ncav) * sizeof(unsigned)) != hipSuccess)
             return set_err(LSR_ENOMEM, "batch allocation failed");
         // the twiddles of each size under the group's FFT plan, FP64-built
@@ -450,6 +453,7 @@ static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind, LaunchEvents 
     const size_t ng = b->grp.size();
     for (size_t i = 0; i < ng; ++i) {
         auto& g = b->grp[i];
+        if (sheet >= g.sheets) continue;   // the group's trip has fewer sheet steps
         const CavDesc* descs = sheet_descs(g, sheet);
         const int v = variant_of(b, g);
         const KernelVariant& kv = g.g->var[v];
@@ -474,9 +478,16 @@ static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind, LaunchEvents 
 // One round trip of every cavity (mode ROW_FIRST or ROW_MID), or the last
 // row pass of a call (ROW_LAST).  With m gain sheets a trip is m steps: the
 // row pass of sheet k (sheet 0 in `mode`, the others as middle passes), then
-// its column pass; the column pass of sheet 0 folds the trip's sums.
+// its column pass; the column pass of sheet 0 folds the trip's sums.  Step k
+// launches the groups whose cavities have more than k sheets.
+static int max_sheets(const lsr_batch_s* b) {
+    int m = 1;
+    for (const auto& g : b->grp) m = std::max(m, g.sheets);
+    return m;
+}
+
 static int launch_trip(lsr_batch_s* b, int mode, LaunchEvents ev) {
-    const int m = mode == ROW_LAST ? 1 : b->sheets;
+    const int m = mode == ROW_LAST ? 1 : max_sheets(b);
     int rc = LSR_OK;
     for (int k = 0; k < m && rc == LSR_OK; ++k) {
         const int md = k == 0 ? mode : ROW_MID;
@@ -489,6 +500,7 @@ static int launch_trip(lsr_batch_s* b, int mode, LaunchEvents ev) {
         const size_t ng = b->grp.size();
         for (size_t i = 0; i < ng && rc == LSR_OK; ++i) {
             auto& g = b->grp[i];
+            if (k >= g.sheets) continue;
             const bool last = md == ROW_LAST;
             const int nt = last ? g.nlast : g.ntasks;
             const int grid = std::min(grid_of(b, g), nt);
@@ -586,7 +598,7 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
     if (same) return LSR_OK;
     for (auto& g : b->grp) {
         std::vector<CavDesc> h;
-        for (int k = 0; k < b->sheets; ++k)
+        for (int k = 0; k < g.sheets; ++k)
         for (int c : g.cav) {
             CavDesc d = plan_sheet_desc(b->plans[c], E[c], N[c], k);
             // only sheet 0's column pass folds the trip's sums into the trace
@@ -622,7 +634,7 @@ static int upload_descs(lsr_batch_s* b, void* const* E, void* const* N, bool for
 // function changed since the batch was grouped: regroup (the kernels of a
 // group read the codes it was built for).
 static int regroup_if_models_changed(lsr_batch_s* b) {
-    bool same = b->models.size() == b->plans.size() && b->sheets == b->plans[0]->slices;
+    bool same = b->models.size() == b->plans.size();
     for (size_t i = 0; same && i < b->plans.size(); ++i) same = b->models[i] == group_code(b->plans[i]);
     if (same) return LSR_OK;
     LSR_HIP(hipStreamSynchronize(b->stream));
@@ -704,8 +716,6 @@ int lsr_batch_create(lsr_batch* out, const lsr_plan* plans, int count) {
         if (plans[i]->prec != PREC_FP64TAB)
             return set_err(LSR_EUNSUPPORTED, "only FP64TAB plans (FP32 field, FP64-built tables) can be batched");
         if (plans[i]->device != plans[0]->device) return set_err(LSR_EINVAL, "plans on different devices");
-        if (plans[i]->slices != plans[0]->slices)
-            return set_err(LSR_EUNSUPPORTED, "plan %d: every plan of a batch must have the same number of gain sheets", i);
         for (int j = 0; j < i; ++j)
             if (plans[j] == plans[i]) return set_err(LSR_EINVAL, "plan %d appears twice", i);
         if (plans[i]->stream != plans[0]->stream)
@@ -811,8 +821,6 @@ int lsr_batch_roundtrips(lsr_batch b, void* const* E, void* const* N, int n_trip
     for (size_t i = 0; i < b->plans.size(); ++i) {
         if (!E[i] || !N[i] || ((uintptr_t)E[i] & 15u) || ((uintptr_t)N[i] & 15u))
             return set_err(LSR_EINVAL, "state %zu: NULL or not 16-byte aligned", i);
-        if (b->plans[i]->slices != b->plans[0]->slices)
-            return set_err(LSR_EUNSUPPORTED, "plan %zu: every plan of a batch must have the same number of gain sheets", i);
     }
     if (check_streams(b)) return LSR_EINVAL;
     if (n_trips == 0) return LSR_OK;
@@ -837,7 +845,8 @@ int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* N, int n_tr
     if (!b || !ms || !E || !N) return set_err(LSR_EINVAL, "bad arguments");
     if (n_trips < 1) return set_err(LSR_EINVAL, "n_trips < 1");
     if (check_streams(b)) return LSR_EINVAL;
-    if (b->plans[0]->slices != 1) return set_err(LSR_EUNSUPPORTED, "kernel timing covers single-sheet batches");
+    for (auto* p : b->plans)
+        if (p->slices != 1) return set_err(LSR_EUNSUPPORTED, "kernel timing covers single-sheet batches");
     DeviceGuard dg(b->device);
     LSR_HIP(hipEventRecord(b->ev_in, b->user));
     LSR_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));

@@ -180,30 +180,57 @@ def test_batched_sheets_fifty_steps_against_the_oracle():
         p.close()
 
 
-def test_batches_need_one_sheet_count_and_bad_counts_are_refused():
-    cavs = sweep(2, seed=3, sizes=(512,))
-    plans = [lsr.Plan(c) for c in cavs]
-    st = [p.state(*initial_state(c)) for p, c in zip(plans, cavs)]
+@pytest.mark.parametrize("engine,k", [(1, 0), (1, 3), (0, 0), (2, 2)])
+def test_batches_mix_sheet_counts(engine, k):
+    """Plans of 1, 2 and 3 gain sheets (two sizes, three local steps) in one
+    batch, on every engine, with and without graphs: plans of one count
+    share groups, sheet step j launches the groups with more than j sheets,
+    and every cavity advances bitwise as on the one-cavity path, its trace
+    included.  Giving a one-sheet plan a second sheet between calls (its
+    inversion split in two) regroups the batch, as on the one-cavity path;
+    kernel timing refuses a batch holding several sheets."""
+    cavs = [c.with_(slices=1 + j % 3, model=c.index % 3) for j, c in enumerate(sweep(6, seed=11, sizes=(512, 1024)))]
+    first, second = 3, 4
+
+    def split(n):
+        return torch.cat([n.unsqueeze(0)] * 2).contiguous() / 2
+
+    ref = []
+    for j, c in enumerate(cavs):
+        p = lsr.Plan(c)
+        e, n = p.state(*initial_state(c))
+        p.roundtrips(e, n, first)
+        if j == 0:
+            lsr.lsr_plan_set_slices(p.handle, 2)
+            n = split(n)
+        p.roundtrips(e, n, second)
+        p.sync()
+        ref.append((e, n, p.trace(second)))
+        p.close()
+    plans, Es, Ns = _sheet_batch(cavs)
     b = lsr.lsr_batch_create([p.handle for p in plans])
+    lsr.lsr_batch_configure(b, engine=engine, graph_k=k)
+    lsr.lsr_batch_roundtrips(b, Es, Ns, first)
+    with pytest.raises(lsr.LsrError) as ei:
+        lsr.lsr_batch_time_kernels(b, Es, Ns, 2)
+    assert ei.value.code == lsr.LSR_EUNSUPPORTED
     lsr.lsr_plan_set_slices(plans[0].handle, 2)
-    with pytest.raises(lsr.LsrError) as ei:
-        lsr.lsr_batch_roundtrips(b, [s[0] for s in st], [s[1] for s in st], 1)
-    assert ei.value.code == lsr.LSR_EUNSUPPORTED
-    with pytest.raises(lsr.LsrError) as ei:
-        lsr.lsr_batch_create([p.handle for p in plans])
-    assert ei.value.code == lsr.LSR_EUNSUPPORTED
-    # the same count on every plan: the batch regroups and runs
-    lsr.lsr_plan_set_slices(plans[1].handle, 2)
-    n2 = [torch.cat([s[1].unsqueeze(0)] * 2).contiguous() / 2 for s in st]
-    lsr.lsr_batch_roundtrips(b, [s[0] for s in st], n2, 2)
-    with pytest.raises(lsr.LsrError) as ei:
-        lsr.lsr_batch_time_kernels(b, [s[0] for s in st], n2, 2)
-    assert ei.value.code == lsr.LSR_EUNSUPPORTED
-    torch.cuda.synchronize()
+    Ns[0] = split(Ns[0])
+    lsr.lsr_batch_roundtrips(b, Es, Ns, second)
+    for p in plans:
+        p.sync()
+    for j, (p, e, n) in enumerate(zip(plans, Es, Ns)):
+        assert torch.equal(e, ref[j][0]) and torch.equal(n, ref[j][1]), (j, cavs[j].slices)
+        assert np.array_equal(p.trace(second), ref[j][2]), j
     lsr.lsr_batch_destroy(b)
-    for bad in (0, -2, lsr.LSR_MAX_SLICES + 1):
-        with pytest.raises(lsr.LsrError) as ei:
-            lsr.lsr_plan_set_slices(plans[1].handle, bad)
-        assert ei.value.code == lsr.LSR_EINVAL
     for p in plans:
         p.close()
+
+
+def test_bad_sheet_counts_are_refused():
+    plan = lsr.Plan(sweep(1, seed=3, sizes=(512,))[0])
+    for bad in (0, -2, lsr.LSR_MAX_SLICES + 1):
+        with pytest.raises(lsr.LsrError) as ei:
+            lsr.lsr_plan_set_slices(plan.handle, bad)
+        assert ei.value.code == lsr.LSR_EINVAL
+    plan.close()
