@@ -450,10 +450,12 @@ static int grid_of(const lsr_batch_s* b, const BatchGroup& g) {
 static const CavDesc* sheet_descs(const BatchGroup& g, int k) { return g.d_desc + (size_t)k * g.cav.size(); }
 
 static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind, LaunchEvents ev = {}, int sheet = 0) {
-    const size_t ng = b->grp.size();
-    for (size_t i = 0; i < ng; ++i) {
-        auto& g = b->grp[i];
-        if (sheet >= g.sheets) continue;   // the group's trip has fewer sheet steps
+    // the groups whose trip has a sheet step `sheet`
+    std::vector<size_t> run;
+    for (size_t i = 0; i < b->grp.size(); ++i)
+        if (sheet < b->grp[i].sheets) run.push_back(i);
+    for (size_t j = 0; j < run.size(); ++j) {
+        auto& g = b->grp[run[j]];
         const CavDesc* descs = sheet_descs(g, sheet);
         const int v = variant_of(b, g);
         const KernelVariant& kv = g.g->var[v];
@@ -461,8 +463,8 @@ static int launch_grouped_pass(lsr_batch_s* b, int mode, int kind, LaunchEvents 
         const int nt = kind == TASK_ROW ? g.nlast : g.ncols;
         // timestamps: start of the first group's dispatch, end of the last's
         LaunchEvents e;
-        if (i == 0) e.start = ev.start;
-        if (i + 1 == ng) e.stop = ev.stop;
+        if (j == 0) e.start = ev.start;
+        if (j + 1 == run.size()) e.stop = ev.stop;
         int rc;
         if (b->tune.engine == 2 && kv.launch_pipe)
             rc = kv.launch_pipe(mode, kind, b->stream, descs, tasks, nt, g.occ_pipe[v][kind] * b->cus, e);
@@ -498,6 +500,10 @@ static int launch_trip(lsr_batch_s* b, int mode, LaunchEvents ev) {
             continue;
         }
         const size_t ng = b->grp.size();
+        // the last group with a sheet step k (at k = m - 1 one with m sheets)
+        size_t last_g = 0;
+        for (size_t i = 0; i < ng; ++i)
+            if (k < b->grp[i].sheets) last_g = i;
         for (size_t i = 0; i < ng && rc == LSR_OK; ++i) {
             auto& g = b->grp[i];
             if (k >= g.sheets) continue;
@@ -505,8 +511,8 @@ static int launch_trip(lsr_batch_s* b, int mode, LaunchEvents ev) {
             const int nt = last ? g.nlast : g.ntasks;
             const int grid = std::min(grid_of(b, g), nt);
             LaunchEvents e;
-            if (i == 0 && k == 0) e.start = ev.start;
-            if (i + 1 == ng && k + 1 == m) e.stop = ev.stop;
+            if (i == 0 && k == 0) e.start = ev.start;   // every group has sheet step 0
+            if (i == last_g && k + 1 == m) e.stop = ev.stop;
             if (g.g->var[variant_of(b, g)].launch(md, grid, b->stream, sheet_descs(g, k), last ? g.d_last : g.d_tasks,
                                                   nt, g.d_ctrl, last ? 1 : b->tune.chunk, e))
                 rc = set_err(LSR_EDEVICE, "persistent kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -919,6 +925,8 @@ void lsr_batch_destroy(lsr_batch b) {
 // Time `trips` persistent trips (graph or eager per the tuning) on scratch
 // state; returns ms per trip or a negative status.
 static double time_batch(lsr_batch_s* b, const std::vector<void*>& E, const std::vector<void*>& N, int trips) {
+    // no groups (a regrouping or repacking failed): nothing would run
+    if (b->grp.empty()) return -1;
     if (upload_descs(b, E.data(), N.data(), false)) return -1;
     // warm-up with the timed call's length: its graphs are captured here,
     // outside the timing
