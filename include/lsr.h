@@ -214,8 +214,7 @@ int lsr_plan_set_transfer(lsr_plan p, const double* T);
  * form groups whose sheet step k is one grouped row pass and one grouped
  * column pass over their cavities (or one persistent launch), and step k
  * launches the groups with more than k sheets; a changed count regroups the
- * batch on its next call.  lsr_batch_time_kernels returns LSR_EUNSUPPORTED
- * for a batch holding a plan with m > 1.
+ * batch on its next call.
  * LSR_EINVAL unless 1 <= m <= LSR_MAX_SLICES. */
 #define LSR_MAX_SLICES 64
 int lsr_plan_set_slices(lsr_plan p, int m);
@@ -417,9 +416,10 @@ int lsr_batch_configure(lsr_batch b, int engine, int variant, int wgs_per_cu, in
  * mean duration of the row-pass launch (all cavities' row blocks of one
  * trip, middle trips only when n_trips > 1), ms[1] = mean column-pass
  * launch, ms[2] = mean round trip from one row-pass start to the next
- * (ms[0] + ms[1] + the gaps between them).  With the persistent
- * engine the whole trip is one launch: ms[0] = ms[2], ms[1] = 0.
- * Synchronises. */
+ * (ms[0] + ms[1] + the gaps between them).  With several gain sheets ms[0]
+ * and ms[1] sum the row and column passes of a trip's sheet steps.  With
+ * the persistent engine the whole trip is one launch per sheet step:
+ * ms[0] = ms[2], ms[1] = 0.  Synchronises. */
 int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* Ninv, int n_trips, double* ms);
 
 void lsr_batch_destroy(lsr_batch b);

@@ -851,18 +851,19 @@ int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* N, int n_tr
     if (!b || !ms || !E || !N) return set_err(LSR_EINVAL, "bad arguments");
     if (n_trips < 1) return set_err(LSR_EINVAL, "n_trips < 1");
     if (check_streams(b)) return LSR_EINVAL;
-    for (auto* p : b->plans)
-        if (p->slices != 1) return set_err(LSR_EUNSUPPORTED, "kernel timing covers single-sheet batches");
     DeviceGuard dg(b->device);
     LSR_HIP(hipEventRecord(b->ev_in, b->user));
     LSR_HIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
     int rc = regroup_if_models_changed(b);
     if (rc == LSR_OK) rc = upload_descs(b, E, N, false);
     if (rc) return rc;
-    // dispatch timestamps of trip t: row pass (or persistent trip kernel)
-    // start/stop = events 4t, 4t+1; column pass start/stop = 4t+2, 4t+3
-    const int ne = 4 * (n_trips + 1);
-    std::vector<hipEvent_t> ev((size_t)ne, nullptr);
+    // dispatch timestamps of sheet step k of trip t (m steps per trip): row
+    // pass (or the persistent kernels of the whole trip) start/stop = events
+    // 4 (m t + k) + 0, 1; column pass start/stop = 4 (m t + k) + 2, 3
+    const int m = max_sheets(b);
+    const size_t ne = 4 * (size_t)m * (size_t)(n_trips + 1);
+    std::vector<hipEvent_t> ev(ne, nullptr);
+    auto at = [&](int t, int k, int j) { return ev[4 * ((size_t)m * t + k) + j]; };
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
             for (auto& x : ev)
@@ -873,11 +874,15 @@ int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* N, int n_tr
     for (int t = 0; t <= n_trips && rc == LSR_OK; ++t) {
         const int mode = t == 0 ? ROW_FIRST : (t == n_trips ? ROW_LAST : ROW_MID);
         if (grouped) {
-            rc = launch_grouped_pass(b, mode, TASK_ROW, LaunchEvents{ev[4 * t], ev[4 * t + 1]});
-            if (rc == LSR_OK && mode != ROW_LAST)
-                rc = launch_grouped_pass(b, mode, TASK_COL, LaunchEvents{ev[4 * t + 2], ev[4 * t + 3]});
+            // the last row pass of a call is sheet 0's alone
+            for (int k = 0; k < (mode == ROW_LAST ? 1 : m) && rc == LSR_OK; ++k) {
+                const int md = k == 0 ? mode : ROW_MID;
+                rc = launch_grouped_pass(b, md, TASK_ROW, LaunchEvents{at(t, k, 0), at(t, k, 1)}, k);
+                if (rc == LSR_OK && md != ROW_LAST)
+                    rc = launch_grouped_pass(b, md, TASK_COL, LaunchEvents{at(t, k, 2), at(t, k, 3)}, k);
+            }
         } else {
-            rc = launch_trip(b, mode, LaunchEvents{ev[4 * t], ev[4 * t + 1]});
+            rc = launch_trip(b, mode, LaunchEvents{at(t, 0, 0), at(t, 0, 1)});
         }
     }
     double row = 0, col = 0, trip = 0;
@@ -885,12 +890,15 @@ int lsr_batch_time_kernels(lsr_batch b, void* const* E, void* const* N, int n_tr
     if (rc == LSR_OK && hipStreamSynchronize(b->stream) == hipSuccess) {
         for (int t = 0; t < n_trips; ++t) {
             if (n_trips > 1 && t == 0) continue;   // the FIRST form differs
-            float a = 0, c = 0, w = 0;
-            (void)hipEventElapsedTime(&a, ev[4 * t], ev[4 * t + 1]);
-            if (grouped) (void)hipEventElapsedTime(&c, ev[4 * t + 2], ev[4 * t + 3]);
-            (void)hipEventElapsedTime(&w, ev[4 * t], ev[4 * t + 4]);
-            row += a;
-            col += c;
+            for (int k = 0; k < (grouped ? m : 1); ++k) {
+                float a = 0, c = 0;
+                (void)hipEventElapsedTime(&a, at(t, k, 0), at(t, k, 1));
+                if (grouped) (void)hipEventElapsedTime(&c, at(t, k, 2), at(t, k, 3));
+                row += a;
+                col += c;
+            }
+            float w = 0;
+            (void)hipEventElapsedTime(&w, at(t, 0, 0), at(t + 1, 0, 0));
             trip += w;
             ++nrow;
         }

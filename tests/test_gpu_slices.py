@@ -187,8 +187,7 @@ def test_batches_mix_sheet_counts(engine, k):
     share groups, sheet step j launches the groups with more than j sheets,
     and every cavity advances bitwise as on the one-cavity path, its trace
     included.  Giving a one-sheet plan a second sheet between calls (its
-    inversion split in two) regroups the batch, as on the one-cavity path;
-    kernel timing refuses a batch holding several sheets."""
+    inversion split in two) regroups the batch, as on the one-cavity path."""
     cavs = [c.with_(slices=1 + j % 3, model=c.index % 3) for j, c in enumerate(sweep(6, seed=11, sizes=(512, 1024)))]
     first, second = 3, 4
 
@@ -211,9 +210,6 @@ def test_batches_mix_sheet_counts(engine, k):
     b = lsr.lsr_batch_create([p.handle for p in plans])
     lsr.lsr_batch_configure(b, engine=engine, graph_k=k)
     lsr.lsr_batch_roundtrips(b, Es, Ns, first)
-    with pytest.raises(lsr.LsrError) as ei:
-        lsr.lsr_batch_time_kernels(b, Es, Ns, 2)
-    assert ei.value.code == lsr.LSR_EUNSUPPORTED
     lsr.lsr_plan_set_slices(plans[0].handle, 2)
     Ns[0] = split(Ns[0])
     lsr.lsr_batch_roundtrips(b, Es, Ns, second)
@@ -225,6 +221,31 @@ def test_batches_mix_sheet_counts(engine, k):
     lsr.lsr_batch_destroy(b)
     for p in plans:
         p.close()
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+def test_kernel_timing_of_mixed_sheets_advances_like_roundtrips(engine):
+    """The profiling form on a batch of 1, 2 and 3 sheets: every sheet step
+    timed, the trips those of lsr_batch_roundtrips, bitwise."""
+    cavs = [c.with_(slices=1 + j % 3) for j, c in enumerate(sweep(3, seed=13, sizes=(512,)))]
+    out = []
+    for timed in (False, True):
+        plans, Es, Ns = _sheet_batch(cavs)
+        b = lsr.lsr_batch_create([p.handle for p in plans])
+        lsr.lsr_batch_configure(b, engine=engine, graph_k=0)
+        if timed:
+            row, col, trip = lsr.lsr_batch_time_kernels(b, Es, Ns, 4)
+            assert row > 0 and trip >= row and (col > 0) == (engine == 1)
+        else:
+            lsr.lsr_batch_roundtrips(b, Es, Ns, 4)
+        for p in plans:
+            p.sync()
+        out.append((Es, Ns))
+        lsr.lsr_batch_destroy(b)
+        for p in plans:
+            p.close()
+    for j in range(len(cavs)):
+        assert torch.equal(out[0][0][j], out[1][0][j]) and torch.equal(out[0][1][j], out[1][1][j]), j
 
 
 def test_bad_sheet_counts_are_refused():
